@@ -1,0 +1,142 @@
+"""FP64 oracle: Hessian diagonals and preconditioners.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/acoustic.py``): no product code may
+import it.
+
+Follows section 1 (Gauss-Newton Hessian, the pseudo-diagonal of eq. (1), the
+Plessix-Mulder aperture-weighted diagonal) and section 3 (Born operator
+eq. (4), extended Born operator eq. (5), its adjoint eq. (6), and the
+subsurface-offset Hessian, of which only the diagonal part is used).
+
+Readings taken where the paper is silent or garbled:
+
+* eq. (1) in the time domain: sum_omega omega^4 |u_s|^2 is, by Parseval,
+  the energy of the second time derivative; its discrete form is
+  E_s(x) = sum_m (D[m](x)/dt^2)^2 dt, H1 = sum_s E_s (no 4/v^6 factor, as
+  printed in eq. (1)).
+* the diagonal of the offset Hessian takes y = x and h_bar = h, with the
+  receiver-side Green's functions replaced by the paper's own
+  frequency-independent aperture factor (the Plessix-Mulder asinh term):
+  D(x, h) = (4 / v(x)^6) sum_s E_s(x + h) A_s(x - h), h horizontal in cells,
+  a term whose x+h or x-h leaves the model contributes 0.
+* A_s(y) = asinh((X_max,s - y_x)/z_y) - asinh((X_min,s - y_x)/z_y), with
+  X_min,s / X_max,s the extreme receiver x-positions (metres) of shot s and
+  z_y = max((iz_y - iz_rec,s) h, h/2) measured from the shallowest receiver
+  of the shot; ``rcv_model='none'`` uses A_s = 1 (the Shin form).
+* preconditioners: P_shot = (4/v^6) H1, P_off(x) = sum_h D(x, h),
+  g_prec = g / (P + eps max P) with eps = 1e-2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .acoustic import Propagator, forward
+
+
+def aperture_factor(grid, rec_iz, rec_ix, model="pm"):
+    """A_s on the model grid [nz][nx] for one shot's receiver spread."""
+    nz, nx, h = grid.nz, grid.nx, grid.dx
+    if model in ("none", 1):
+        return np.ones((nz, nx))
+    rec_iz = np.asarray(rec_iz)
+    rec_ix = np.asarray(rec_ix)
+    xmin = float(rec_ix.min()) * h
+    xmax = float(rec_ix.max()) * h
+    iz_rec = int(rec_iz.min())
+    z = np.maximum((np.arange(nz) - iz_rec) * h, 0.5 * h)[:, None]
+    x = (np.arange(nx) * h)[None, :]
+    return np.arcsinh((xmax - x) / z) - np.arcsinh((xmin - x) / z)
+
+
+def offset_diag(v, E_list, A_list, hmax):
+    """D[h + hmax][z][x] = (4/v^6) sum_s E_s(z, x+h) A_s(z, x-h)."""
+    v = np.asarray(v, np.float64)
+    nz, nx = v.shape
+    D = np.zeros((2 * hmax + 1, nz, nx))
+    for E, A in zip(E_list, A_list):
+        for h in range(-hmax, hmax + 1):
+            # x such that 0 <= x+h < nx and 0 <= x-h < nx
+            lo, hi = abs(h), nx - abs(h)
+            if lo >= hi:
+                continue
+            xs = np.arange(lo, hi)
+            D[h + hmax][:, xs] += E[:, xs + h] * A[:, xs - h]
+    return D * (4.0 / v ** 6)[None]
+
+
+def shot_scaling(v, H1):
+    """P_shot = (4/v^6) H1."""
+    v = np.asarray(v, np.float64)
+    return 4.0 / v ** 6 * H1
+
+
+def offset_scaling(D):
+    """P_off(x) = sum_h D(x, h)."""
+    return np.sum(D, axis=0)
+
+
+def precondition(g, P, eps=1e-2):
+    """g / (P + eps * max P)."""
+    P = np.asarray(P, np.float64)
+    return np.asarray(g, np.float64) / (P + eps * P.max())
+
+
+# --------------------------------------------------------------------------
+# exact diagonals by explicit (extended) Born columns -- small grids only
+# --------------------------------------------------------------------------
+def extended_born_columns(v, grid, shot, wavelet, cells, kind="l2"):
+    """Columns of the discretised extended Born operator (eq. (5)).
+
+    For each (iz, ix, h) in ``cells`` the column is the recorded response
+    to the model perturbation delta_v(x, h) = 1: the perturbation wavefield
+    obeys the same scheme, started from zero, and in the update that yields
+    du[m] it receives q(x-h) (2 / v(x)^3) D[m](x+h) at cell x-h, where
+    D[m] = u[m] - 2u[m-1] + u[m-2] of the background wavefield u.  The source
+    side is read at x+h, the receiver side enters at x-h and 2/v^3 is taken at
+    the centre, as in eq. (5).  Returns [ncol, nrec, nt]; with kind='int' the
+    time-integral weighting of eq. (2) (dt * running sum) is applied."""
+    siz, six, riz, rix, nt = shot
+    N = grid.nsponge
+    v = np.asarray(v, np.float64)
+    hist = []
+    forward(v, grid, shot, wavelet, keep=hist)          # hist[n+1] = u[n]
+    prop = Propagator(v, grid)
+    ncol = len(cells)
+    Z, X = prop.q.shape
+    rz, rx = prop.cell(np.asarray(riz), np.asarray(rix))
+    col = np.arange(ncol)
+    inj_z = np.array([c[0] + N for c in cells])
+    inj_x = np.array([c[1] - c[2] + N for c in cells])          # x - h
+    src_x = np.array([c[1] + c[2] + N for c in cells])          # x + h
+    for (iz, ix, h) in cells:
+        assert 0 <= ix - h < grid.nx and 0 <= ix + h < grid.nx and 0 <= iz < grid.nz
+    cen_v = np.array([v[c[0], c[1]] for c in cells])
+    # step() adds dt^2 q (L du + extra): extra = (2/v^3) D / dt^2 gives q (2/v^3) D
+    coef = 2.0 / cen_v ** 3 / (grid.dt ** 2)
+    du_prev = np.zeros((ncol, Z, X))
+    du = np.zeros((ncol, Z, X))
+    out = np.zeros((ncol, len(riz), nt))
+    for n in range(nt - 1):
+        m = n + 1
+        Dm = hist[m + 1] - 2.0 * hist[m] + hist[m - 1]          # D[m]
+        extra = np.zeros((ncol, Z, X))
+        extra[col, inj_z, inj_x] = coef * Dm[inj_z, src_x]
+        dun = prop.step(du, du_prev, extra)
+        du_prev, du = du, dun
+        out[:, :, m] = du[:, rz, rx]
+    if kind in ("int", 1):
+        out = grid.dt * np.cumsum(out, axis=-1)
+    return out
+
+
+def offset_diag_exact(v, grid, geom, wavelet, cells, kind="l2"):
+    """D_exact(x, h) = sum over shots, receivers, samples of the squared
+    extended-Born column entries; at h = 0 this is diag(J^T J) of the
+    Gauss-Newton Hessian.  ``cells`` is a list of (iz, ix, h)."""
+    total = np.zeros(len(cells))
+    for s in range(geom.nshot):
+        shot = geom.shot(s)
+        w = wavelet[s] if np.ndim(wavelet) == 2 else wavelet
+        cols = extended_born_columns(v, grid, shot, np.asarray(w, np.float64), cells, kind)
+        total += np.sum(cols * cols, axis=(1, 2))
+    return total
