@@ -1,0 +1,249 @@
+"""Throughput of the batched, autograd FWI gradient on one MI355X.
+
+One step = the whole hot path over the 1024x384 layered workload (64 shots,
+512 receivers each, nt = 4000, dt = 1 ms, Ricker 8 Hz), inputs resident in
+HBM: model prep, forward sweep of every shot with sqrt(nt) snapshots and
+boundary strips, time-integral misfit and adjoint source (eq. (2)), the fused
+backward sweep (source-wavefield reconstruction, adjoint propagation,
+zero-lag imaging, eq. (1) illumination), the per-shot Hessian epilogue (H1 and
+the offset diagonal, |h| <= 16) and the shot-scaling preconditioned gradient,
+driven through torch.autograd (J.backward()).
+
+Prints one JSON line.  `value` is shot-gradients per second; the line also
+carries Gcell-updates/s, the roofline of the dominant kernel (the fused
+reverse step), the plain per-shot GPU path on a subset of shots, and the FP64
+oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=64, help="shots of the workload (64 = the full workload)")
+    ap.add_argument("--plain-shots", type=int, default=4)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=150, help="time steps of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM counters)")
+    return ap.parse_args()
+
+
+def reverse_bytes_per_shot_step(grid, nrec):
+    """Algorithmic HBM bytes of one fused reverse step of one shot (FP32):
+    model cells read u[m], u[m-1], lam[m+1], lam[m+2], w, g, E and write
+    u[m-2], lam[m], g, E (44 B); the 4-cell strip ring reads its strip value
+    and writes u besides the adjoint update (24 B); other sponge cells only
+    advance the adjoint wavefield (16 B); receivers read psi (4 B)."""
+    nz, nx, N = grid.nz, grid.nx, grid.nsponge
+    model = nz * nx
+    padded = (nz + 2 * N) * (nx + 2 * N)
+    ring = 8 * (nz + nx)
+    return 44 * model + 24 * ring + 16 * (padded - model - ring) + 4 * nrec
+
+
+def forward_bytes_per_shot_step(grid, nrec, K):
+    nz, nx, N = grid.nz, grid.nx, grid.nsponge
+    model = nz * nx
+    padded = (nz + 2 * N) * (nx + 2 * N)
+    ring = 8 * (nz + nx)
+    return 16 * padded + 4 * ring + 8 * model / K + 4 * nrec
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("fwi_kernels.hip", "fwi_internal.h"):
+        with open(os.path.join(ROOT, "paper_1406_1864_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kname, bytes_per_launch):
+    """Per-launch HBM bytes from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kname}_pmc_layered_1024x384.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        p = json.load(fh)
+    if p.get("kernel_source_sha") != kernel_hash():
+        return None
+    return p.get("bytes_per_launch")
+
+
+def cpu_baseline(w, nsteps):
+    """The FP64 oracle as it stands, one shot, first `nsteps` time steps."""
+    import oracle
+    from paper_1406_1864_amd.synthetic import Grid
+    geom = w.geom.subset([0]).with_nt(nsteps)
+    grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, nsteps, w.grid.nsponge, w.grid.v_ref)
+    d_obs = np.zeros((geom.ntrace, nsteps), np.float32)
+    t0 = time.perf_counter()
+    oracle.gradient(w.v_start, grid, geom, w.wavelet[:nsteps], d_obs, "int")
+    dt = time.perf_counter() - t0
+    Z, X = grid.padded
+    nt_full = int(w.geom.nt[0])
+    per_shot = dt * (nt_full - 1) / (nsteps - 1)
+    return {"value": 1.0 / per_shot, "unit": "shot-gradients/s", "cores": 1, "kind": "oracle",
+            "gcell_updates_per_s": 3.0 * Z * X * (nsteps - 1) / dt / 1e9,
+            "seconds": dt,
+            "sample": f"1 of {w.geom.nshot} shots, first {nsteps} of {nt_full} time steps "
+                      f"(FP64 NumPy, single thread), extrapolated linearly to the full record"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by shots and "
+              "multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1406_1864_amd import binding as B
+    from paper_1406_1864_amd.autograd import FWIProblem, fwi_misfit
+    from paper_1406_1864_amd.synthetic import layered_1024x384
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    B.load()
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    w = layered_1024x384()
+    if args.shots != w.geom.nshot:
+        w.geom = w.geom.subset(range(args.shots))
+    grid, geom = w.grid, w.geom
+    HM = 16
+    print(f"# workload {w.name}: {geom.nshot} shots, grid {grid.nz}x{grid.nx}, nt {grid.nt_max}", file=sys.stderr,
+          flush=True)
+
+    # recorded data: modelled from the true model with the same engine
+    d_obs = B.forward(w.v_true, w.wavelet, grid, geom, B.make_exec(), device=dev)
+    ex = B.make_exec(autotune=1)
+    pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
+    v = torch.tensor(w.v_start, device=dev, requires_grad=True)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    phase = np.zeros(3)
+
+    def step(timed):
+        v.grad = None
+        if timed:
+            ev[0].record()
+        J = fwi_misfit(v, pr)
+        if timed:
+            ev[1].record()
+        J.backward()
+        if timed:
+            ev[2].record()
+        gp = B.precondition(v.detach(), v.grad, pr.illum, grid, B.PRECOND_SHOT, device=dev)
+        if timed:
+            ev[3].record()
+            torch.cuda.synchronize()
+            phase[0] += ev[0].elapsed_time(ev[1])
+            phase[1] += ev[1].elapsed_time(ev[2])
+            phase[2] += ev[2].elapsed_time(ev[3])
+        return J, gp
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        J, gp = step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    assert torch.isfinite(J).item() and bool(torch.isfinite(gp).all())
+
+    Z, X = grid.padded
+    nt = geom.nt.astype(np.int64)
+    shots = geom.nshot
+    cell_updates = float(np.sum(3 * Z * X * nt))
+    value = shots / (wall / args.steps)
+    nrec = np.diff(geom.rec_ptr)
+    rev_bytes = float(sum((nt[s] - 1) * reverse_bytes_per_shot_step(grid, int(nrec[s])) for s in range(shots)))
+    rev_ms = phase[1] / args.steps
+    achieved = rev_bytes / (rev_ms * 1e-3) / 1e9
+    fwd_K = int(np.ceil(np.sqrt(nt.max())))
+    fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
+                          for s in range(shots)))
+    traffic = measured_traffic("k_reverse", None)
+    out = {
+        "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
+        "value": value,
+        "unit": "shot-gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name if shots == 64 else f"{w.name} ({shots} shots)", "shots": shots,
+                   "grid": [grid.nz, grid.nx], "padded": [Z, X], "nt": int(nt.max()), "receivers_per_shot": 512,
+                   "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned"},
+        "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
+        "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
+                     "precondition": phase[2] / args.steps},
+        "roofline": {"bound": "hbm", "kernel": "k_reverse", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_shot_step": reverse_bytes_per_shot_step(grid, 512)},
+        "forward_roofline": {"achieved": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9, "unit": "GB/s",
+                             "frac": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
+
+    if not args.no_plain:
+        ps = min(args.plain_shots, shots)
+        pgeom = geom.subset(range(ps))
+        pd = d_obs[:pgeom.ntrace].contiguous()
+        ppr = FWIProblem(grid, pgeom, w.wavelet, pd, "int", B.make_exec(mode=B.EXEC_PLAIN), illum=True, hmax=HM,
+                         device=dev)
+        vp = torch.tensor(w.v_start, device=dev, requires_grad=True)
+
+        def pstep():
+            vp.grad = None
+            Jp = fwi_misfit(vp, ppr)
+            Jp.backward()
+            return B.precondition(vp.detach(), vp.grad, ppr.illum, grid, B.PRECOND_SHOT, device=dev)
+
+        pstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pstep()
+        torch.cuda.synchronize()
+        pt = time.perf_counter() - t0
+        out["plain"] = {"value": ps / pt, "unit": "shot-gradients/s", "shots": ps,
+                        "path": "one shot per launch, one launch per time step, no graph"}
+        out["speedup_vs_plain"] = value / (ps / pt)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

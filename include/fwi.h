@@ -1,0 +1,210 @@
+/*
+ * fwi.h -- C ABI of libfwi: the preconditioned FWI gradient hot path on MI355X.
+ *
+ * Method: Huang, Wang & Ren, "Two new gradient precondition schemes for full
+ * waveform inversion".  The library computes, for a 2D constant-density
+ * acoustic medium and many shots,
+ *   - the forward wavefield and the recorded traces (section 2: d is recorded,
+ *     u is synthesised by the constant-density acoustic equation);
+ *   - the least-squares misfit J(v) with W_d = I (section 2) or the
+ *     time-integral weighting of eq. (2);
+ *   - the gradient dJ/dv by the adjoint-state method: zero-lag
+ *     cross-correlation of the second time difference of the source wavefield
+ *     with the back-propagated adjoint wavefield, times 2/v^3 (section 2; for
+ *     eq. (2) the exact discrete counterpart of eq. (3));
+ *   - the source-illumination pseudo-diagonal Hessian of eq. (1);
+ *   - the diagonal part of the localized subsurface-offset Hessian of
+ *     section 3, with the aperture factor of the Plessix-Mulder diagonal
+ *     (section 1) standing in for the receiver-side Green's functions;
+ *   - the gradient scaled by either diagonal (section 3.1, shot scaling and
+ *     sub-offset Hessian scaling).
+ *
+ * Discretisation (the paper names only a time-domain finite-difference
+ * engine): 8th-order 17-point Laplacian, leapfrog in time, an N-cell damping
+ * sponge padded outside the model on all four sides (v edge-replicated),
+ *   (1+g) u[n+1] = 2u[n] - (1-g) u[n-1] + dt^2 v^2 (L u[n] + f[n] e_src / h^2),
+ * u[0] = u[-1] = 0, g = (dt/2) eta_max (d/N)^2, eta_max = 3 v_ref ln(1000)/(2 N h),
+ * receivers record u[n] for n = 0 .. nt-1.  The gradient is taken with respect
+ * to the model cells with the sponge padding held fixed.
+ *
+ * Conventions shared by every entry point
+ *   - SI units; model grid [nz][nx], row-major, x contiguous, dz == dx.
+ *   - Device pointers (v, wavelet, data, outputs, workspace) are caller-owned
+ *     HIP device memory on the current device.  Geometry arrays inside
+ *     fwi_geometry are HOST pointers; they are read during the call only.
+ *   - The library never allocates device memory: all scratch lives in the
+ *     caller's workspace, sized by fwi_workspace_bytes().
+ *   - Calls are asynchronous on `hip_stream` (a hipStream_t, NULL = default
+ *     stream).  Do not run two calls concurrently on the same workspace.
+ *   - Return 0 on success or a negative FWI_ERR_* code.  Every host-side check
+ *     (arguments, geometry, CFL bound, workspace size) happens before anything
+ *     is enqueued.  On error the outputs are unspecified; fwi_last_error()
+ *     returns a thread-local message.  No C++ exception crosses the ABI.
+ *   - Results are deterministic: repeated calls with the same inputs and
+ *     execution settings are bitwise identical.
+ */
+#ifndef FWI_H
+#define FWI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define FWI_OK              0
+#define FWI_ERR_ARG        -1   /* null pointer, bad enum, non-positive size   */
+#define FWI_ERR_GEOM       -2   /* source/receiver outside the model, bad CSR,
+                                   nt[s] outside [2, nt_max], duplicate receiver
+                                   cell within one shot                          */
+#define FWI_ERR_CFL        -3   /* v_ref * dt / dx above the scheme's bound      */
+#define FWI_ERR_WORKSPACE  -4   /* workspace smaller than fwi_workspace_bytes()  */
+#define FWI_ERR_HIP        -5   /* a HIP runtime call failed                     */
+#define FWI_ERR_NONFINITE  -6   /* (fwi_status) v non-finite, <= 0 or above the
+                                   CFL bound on the device                       */
+#define FWI_ERR_STATE      -7   /* fwi_misfit_backward without a matching
+                                   fwi_misfit_forward in the same workspace      */
+
+/* Stability bound of the scheme: v dt / h <= 2 / sqrt(2 * 6.50155). */
+#define FWI_CFL_LIMIT 0.5546324796655889
+
+/* ---------------------------------------------------------------- inputs */
+typedef struct {
+    int32_t nz, nx;     /* model cells (rows, columns)                         */
+    float   dx;         /* grid spacing h in metres (dz == dx)                 */
+    float   dt;         /* time step in seconds                                */
+    int32_t nt_max;     /* trace length / stride of wavelet and data rows      */
+    int32_t nsponge;    /* sponge width N in cells, >= 4                       */
+    float   v_ref;      /* sponge reference velocity (m/s), also the declared
+                           maximum velocity used for the CFL check             */
+} fwi_grid;
+
+typedef struct {
+    int32_t nshot;              /* number of shots, >= 0                        */
+    const int32_t *src_iz;      /* [nshot] source cell rows    (0 <= iz < nz)   */
+    const int32_t *src_ix;      /* [nshot] source cell columns (0 <= ix < nx)   */
+    const int32_t *rec_ptr;     /* [nshot+1] CSR: shot s owns receivers
+                                   rec_ptr[s] .. rec_ptr[s+1]-1; rec_ptr[0] = 0 */
+    const int32_t *rec_iz;      /* [rec_ptr[nshot]] receiver rows               */
+    const int32_t *rec_ix;      /* [rec_ptr[nshot]] receiver columns            */
+    const int32_t *nt;          /* [nshot] record length of each shot, 2..nt_max;
+                                   NULL = nt_max for every shot                  */
+} fwi_geometry;
+
+/* Execution settings (all fields 0 = automatic). */
+typedef struct {
+    int32_t mode;             /* FWI_EXEC_BATCHED (default) or FWI_EXEC_PLAIN:
+                                 plain = one shot at a time, one launch per
+                                 time step, no graph, no autotuning            */
+    int32_t shots_in_flight;  /* shots advanced together by one launch         */
+    int32_t tile_rows;        /* rows of one wavefront's tile (z sweep length) */
+    int32_t graph_steps;      /* time steps per captured hipGraph chunk;
+                                 -1 = do not use graphs                        */
+    int32_t autotune;         /* 1 = pick unset fields by timing (cached per
+                                 grid/geometry); 0 = heuristic defaults        */
+} fwi_exec;
+
+enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
+enum { FWI_MISFIT_L2 = 0,              /* section 2, W_d = I                   */
+       FWI_MISFIT_TIME_INTEGRAL = 1 }; /* eq. (2), W_d u = dt * running sum     */
+enum { FWI_HESS_EQ1 = 0,               /* eq. (1): H1 = sum_s E_s              */
+       FWI_HESS_OFFSET = 1 };          /* offset diagonal D[2H+1][nz][nx]      */
+enum { FWI_RCV_PM = 0,                 /* Plessix-Mulder aperture factor A_s   */
+       FWI_RCV_NONE = 1 };             /* A_s = 1 (Shin form)                  */
+enum { FWI_PRECOND_SHOT = 0,           /* P = (4/v^6) H1                       */
+       FWI_PRECOND_OFFSET = 1 };       /* P = sum_h D(x, h)                    */
+/* `what` argument of fwi_workspace_bytes */
+enum { FWI_WS_FORWARD = 0, FWI_WS_GRADIENT = 1, FWI_WS_HESSIAN = 2,
+       FWI_WS_AUTOGRAD = 3, FWI_WS_PRECOND = 4 };
+
+/* ---------------------------------------------------------------- sizing */
+/* Bytes of device workspace needed by the matching entry point (hmax: offset
+ * range of the offset diagonal, 0 if unused).  Returns 0 if the arguments fail
+ * validation (see fwi_last_error).  FWI_WS_AUTOGRAD sizes the pair
+ * fwi_misfit_forward / fwi_misfit_backward, which keeps the checkpoints of
+ * every shot between the two calls. */
+size_t fwi_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
+                           const fwi_exec *exec, int what, int hmax);
+
+/* Host-side validation only (no HIP call).  Returns 0 or FWI_ERR_*. */
+int fwi_validate(const fwi_grid *grid, const fwi_geometry *geom);
+
+/* ---------------------------------------------------------------- compute */
+/* Forward modelling (section 2, u synthesised by the acoustic equation).
+ *   v        [nz][nx] float, m/s
+ *   wavelet  [nshot][nt_max] float with row stride `wavelet_stride` floats;
+ *            stride 0 = one wavelet shared by all shots
+ *   data     [rec_ptr[nshot]][nt_max] float out: data[r][n] = u[n] at
+ *            receiver r, zero for n >= nt[s]                                 */
+int fwi_forward(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                const float *v, const float *wavelet, int64_t wavelet_stride,
+                float *data, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Misfit and gradient (section 2, eq. (2), eq. (3)).
+ *   d_obs       [rec_ptr[nshot]][nt_max] recorded data (samples n >= nt[s]
+ *               are ignored)
+ *   misfit      FWI_MISFIT_L2 or FWI_MISFIT_TIME_INTEGRAL
+ *   J           device double out: J = 1/2 sum (W_d r)^2 over shots,
+ *               receivers and samples, r = synthetic - recorded
+ *   grad        [nz][nx] float out: dJ/dv on model cells
+ *   illum       [nz][nx] float out or NULL: H1 = sum_s sum_m (D_m/dt^2)^2 dt,
+ *               D_m = u[m] - 2u[m-1] + u[m-2]   (eq. (1), time-domain form)
+ *   offset_diag [2*hmax+1][nz][nx] float out or NULL: slice h + hmax holds
+ *               D(x, h) = (4/v(x)^6) sum_s E_s(x + h) A_s(x - h), h in cells
+ *               along x, terms leaving the model are 0 (section 3, diagonal
+ *               part); rcv_model selects A_s                                  */
+int fwi_gradient(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                 const float *v, const float *wavelet, int64_t wavelet_stride,
+                 const float *d_obs, int misfit,
+                 double *J, float *grad, float *illum,
+                 int hmax, int rcv_model, float *offset_diag,
+                 void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Hessian diagonals from the forward wavefield alone (no adjoint pass).
+ *   kind FWI_HESS_EQ1:    diag [nz][nx]            = H1            (eq. (1))
+ *   kind FWI_HESS_OFFSET: diag [2*hmax+1][nz][nx]  = D(x, h)       (section 3) */
+int fwi_hessian_diag(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                     const float *v, const float *wavelet, int64_t wavelet_stride,
+                     int kind, int hmax, int rcv_model, float *diag,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* The gradient split in two for reverse-mode differentiation of J(v).
+ * fwi_misfit_forward runs the forward sweep of every shot, keeps each shot's
+ * sqrt(nt) snapshots and per-step boundary strips in the workspace, and writes
+ * J.  fwi_misfit_backward then runs the adjoint sweep from those checkpoints
+ * and writes grad = (*grad_scale) dJ/dv (grad_scale: device double, NULL = 1)
+ * plus the optional Hessian diagonals.  Both calls must receive the same
+ * grid, geometry, exec, v, wavelet and workspace (FWI_WS_AUTOGRAD size);
+ * otherwise fwi_misfit_backward returns FWI_ERR_STATE. */
+int fwi_misfit_forward(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                       const float *v, const float *wavelet, int64_t wavelet_stride,
+                       const float *d_obs, int misfit, double *J,
+                       void *workspace, size_t ws_bytes, void *hip_stream);
+int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                        const float *v, const float *wavelet, int64_t wavelet_stride,
+                        const double *grad_scale, float *grad, float *illum,
+                        int hmax, int rcv_model, float *offset_diag,
+                        void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Preconditioned gradient (section 3.1): out = grad / (P + eps * max P) with
+ * P = (4/v^6) * hdiag (kind SHOT, hdiag = H1 [nz][nx]) or
+ * P = sum_h hdiag[h] (kind OFFSET, hdiag = D [2*hmax+1][nz][nx]).
+ * workspace: at least fwi_workspace_bytes(..., FWI_WS_PRECOND, hmax) bytes. */
+int fwi_precondition(const fwi_grid *grid, const float *v, const float *grad,
+                     int kind, const float *hdiag, int hmax, float eps, float *out,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Synchronises `hip_stream` and returns FWI_ERR_NONFINITE if the last call
+ * that used this workspace found a non-finite, non-positive or over-CFL
+ * velocity on the device (its outputs are then unspecified), else 0. */
+int fwi_status(const void *workspace, void *hip_stream);
+
+/* Thread-local description of the last error returned on this thread. */
+const char *fwi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWI_H */

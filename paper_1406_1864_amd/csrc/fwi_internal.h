@@ -1,0 +1,130 @@
+// Internal data layout shared by the host runtime and the gfx950 kernels of
+// libfwi.  Nothing here is part of the public ABI.
+//
+// Storage of one padded field level (Z = nz + 2N rows, X = nx + 2N columns):
+// row-major with pitch P floats; padded column x lives at storage column
+// x + off, where `off` is chosen so that the model's first column (x = N)
+// starts a 64-float (256-byte) line.  Storage columns outside [off, off + X)
+// are held at zero and implement the zero boundary beyond the sponge.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace fwi {
+
+constexpr int kWave = 64;         // CDNA wavefront width == tile width in x
+constexpr int kWavesPerBlock = 4;  // independent wavefronts per workgroup
+constexpr int kRadius = 4;         // stencil half-width (8th order)
+
+struct Dims {
+  int32_t nz, nx, N;     // model rows / columns, sponge width
+  int32_t Z, X;          // padded rows / columns
+  int32_t P, off;        // storage pitch (floats) and column offset
+  int32_t mx0;           // storage column of model column 0 (multiple of 64)
+  int32_t XT, ZT, TZ;    // wave tiles along x and z, rows per tile
+  int32_t ring;          // floats of one boundary-strip ring: 8 (nx + nz)
+  int64_t field;         // floats per field level: Z * P
+  int64_t model;         // floats per model-grid array: nz * nx
+};
+
+struct ShotDesc {
+  int32_t nt;          // record length
+  int32_t K;           // snapshot spacing
+  int32_t nsnap;       // snapshot pairs kept
+  int32_t src_z;       // padded row of the source cell
+  int32_t src_xs;      // storage column of the source cell
+  int32_t rec_begin;   // first global trace index of the shot
+  int32_t nrec;        // receivers of the shot
+  int32_t rdir;        // first receiver-map directory entry (one per x tile)
+  int32_t rec_z0;      // shallowest receiver row (model rows)
+  float xmin_m, xmax_m;  // receiver aperture in metres
+  int32_t pad_;
+};
+
+struct SlotInfo {
+  int32_t shot;  // shot index or -1 (idle slot)
+  int32_t cs;    // checkpoint set: index of the u fields / snapshots / strips
+};
+
+struct RmapDir { int32_t begin, count; };  // per (shot, x tile): rows in RmapRow
+struct RmapRow { int32_t z, map; };         // padded row; offset of a 64-entry map
+
+// Kernel arguments of one time step over a batch of shots.
+struct StepArgs {
+  Dims d;
+  int32_t S;            // slots in the launch
+  int32_t xcd_map;      // 1: keep each slot's tiles on one XCD
+  const SlotInfo* slots;
+  const ShotDesc* shots;
+  const RmapDir* rdir;
+  const RmapRow* rrows;
+  const int32_t* rmaps;
+  const float* w;       // dt^2 v^2 / h^2 on the padded grid (storage layout)
+  float* u;             // [cs][2][field]   source wavefield, two time levels
+  float* lam;           // [slot][2][field] adjoint wavefield
+  float* g;             // [slot][model]    sum_m lam[m] D[m]
+  float* E;             // [slot][model]    sum_m D[m]^2
+  float* traces;        // [nt_max][ntrace] recorded u (forward) / psi' (adjoint)
+  int32_t ntrace;
+  const float* wavelet;
+  int64_t wstride;
+  float* snap;          // [cs] blocks of snap_stride floats: [nsnap][2][model]
+  float* strip;         // [cs] blocks of strip_stride floats: [nt][ring]
+  int64_t snap_stride, strip_stride;
+  double sp_a;          // sponge damping g = sp_a * d^2 (d: cells into sponge)
+  const int32_t* step_ctr;  // device step base (graph replay) or null
+  int32_t step;             // step offset, or absolute step if step_ctr is null
+  const int32_t* err;       // device error flag: nonzero = skip all work
+};
+
+// forward-kernel feature flags
+enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4 };
+
+struct MisfitArgs {
+  const SlotInfo* slots;
+  const ShotDesc* shots;
+  float* traces;        // in: recorded synthetic u (time-major); out: psi'
+  const float* dobs;    // [ntrace][nt_max]
+  int32_t ntrace, nt_max, kind;
+  double dt, psi_scale;
+  double* Jpart;        // [ntrace]
+  const int32_t* err;
+};
+
+struct EpiArgs {
+  Dims d;
+  int32_t S;
+  const SlotInfo* slots;
+  const ShotDesc* shots;
+  const float* E;       // [slot][model]
+  const float* v;       // [nz][nx]
+  float* H1;            // [nz][nx] or null
+  float* D;             // [2H+1][nz][nx] or null
+  int32_t hmax, rcv_none;
+  float h, inv_dt3;
+  const int32_t* err;
+};
+
+// host-side launchers (fwi_kernels.hip)
+hipError_t launch_prep(const Dims& d, const float* v, float* w, float dt, float h, float vmax,
+                       int32_t* err, hipStream_t s);
+hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s);
+hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,
+                             int S, int use_cs, hipStream_t s);
+hipError_t launch_forward(const StepArgs& a, int flags, hipStream_t s);
+hipError_t launch_reverse(const StepArgs& a, hipStream_t s);
+hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);
+hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s);
+hipError_t launch_misfit(const MisfitArgs& a, int S, int max_nrec, hipStream_t s);
+hipError_t launch_reduce_J(const double* part, int n, double* J, const int32_t* err, hipStream_t s);
+hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s);
+hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const float* v,
+                               const double* scale, float* grad, const int32_t* err, hipStream_t s);
+hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
+                             const int32_t* trace_shot, float* data, hipStream_t s);
+hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int kind,
+                          const float* hdiag, int hmax, float eps, float* out, uint32_t* maxbits,
+                          hipStream_t s);
+
+}  // namespace fwi

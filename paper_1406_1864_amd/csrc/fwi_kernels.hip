@@ -1,0 +1,715 @@
+// gfx950 kernels of libfwi: 2D acoustic 8th-order/leapfrog time stepping
+// with the fused adjoint-state gradient and Hessian-diagonal accumulations.
+//
+// Method: Huang, Wang & Ren, "Two new gradient precondition schemes for full
+// waveform inversion" -- section 2 (least-squares misfit, zero-lag
+// cross-correlation gradient scaled by 2/v^3), eq. (2) and eq. (3) (the
+// time-integral misfit and its adjoint-state gradient), eq. (1) (source
+// illumination pseudo-diagonal Hessian) and section 3 (diagonal part of the
+// subsurface-offset Hessian).  The discrete scheme is stated in include/fwi.h.
+//
+// Execution model (memory-bound stencil, no MFMA):
+//   * one wavefront owns a 64-column tile of one shot and sweeps it along z,
+//     keeping the 9 rows of the vertical stencil in registers (register
+//     sliding); the +-4 horizontal neighbours come from a per-wavefront LDS
+//     row with a 4-column halo on each side;
+//   * a launch advances every shot of a batch by one time step; a block holds
+//     4 independent wavefronts (no block barrier), and with 8k shots in the
+//     batch all tiles of a shot stay on one XCD, so stencil halos are re-read
+//     from that XCD's L2;
+//   * interior cells use an FP32 difference-form Laplacian
+//     sum_k c_k ((neighbours at distance k) - 4u) and one FMA update; sponge
+//     cells are updated in FP64 (the damping coefficients are the error
+//     source of an all-FP32 scheme).  Fields stay FP32 in HBM.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "fwi_internal.h"
+
+namespace fwi {
+
+// 8th-order second-derivative weights c1..c4 (c0 = -4 * (c1+..+c4)/2 folded
+// into the difference form)
+constexpr float kC1 = 8.0f / 5.0f;
+constexpr float kC2 = -1.0f / 5.0f;
+constexpr float kC3 = 8.0f / 315.0f;
+constexpr float kC4 = -1.0f / 560.0f;
+
+__device__ __forceinline__ float ck(int k) {
+  return k == 1 ? kC1 : (k == 2 ? kC2 : (k == 3 ? kC3 : kC4));
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Wavefront-local LDS exchange: LDS operations of one wavefront complete in
+// program order, so only compiler reordering has to be prevented.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// blockIdx/wave -> (slot, tile).  Tiles of one slot are numbered x-fastest.
+__device__ __forceinline__ bool map_tile(const Dims& d, int S, int xcd_map, int wave,
+                                         int& slot, int& tile) {
+  const int T = d.XT * d.ZT;
+  const int bps = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int b = blockIdx.x;
+  int tb;
+  if (xcd_map) {
+    // consecutive block ids go to consecutive XCDs: give XCD c the slots
+    // c, c+8, c+16, ... so that neighbouring tiles share one L2
+    const int xcd = b & 7, r = b >> 3;
+    slot = (r / bps) * 8 + xcd;
+    tb = r % bps;
+  } else {
+    slot = b / bps;
+    tb = b % bps;
+  }
+  tile = tb * kWavesPerBlock + wave;
+  return slot < S && tile < T;
+}
+
+__device__ __forceinline__ int step_of(const StepArgs& a) {
+  return a.step_ctr ? (*a.step_ctr + a.step) : a.step;
+}
+
+// boundary-strip index of padded cell (z, x) or -1 (ring: the 4 cells just
+// outside the model on each side, corners excluded)
+__device__ __forceinline__ int ring_index(const Dims& d, int z, int x) {
+  const int mz = z - d.N, mx = x - d.N;
+  const bool zin = mz >= 0 && mz < d.nz, xin = mx >= 0 && mx < d.nx;
+  if (xin && mz >= -kRadius && mz < 0) return (mz + kRadius) * d.nx + mx;
+  if (xin && mz >= d.nz && mz < d.nz + kRadius) return 4 * d.nx + (mz - d.nz) * d.nx + mx;
+  if (zin && mx >= -kRadius && mx < 0) return 8 * d.nx + mz * 4 + (mx + kRadius);
+  if (zin && mx >= d.nx && mx < d.nx + kRadius) return 8 * d.nx + 4 * d.nz + mz * 4 + (mx - d.nx);
+  return -1;
+}
+
+// -------------------------------------------------------------------------
+// forward step: u[n+1] from u[n], u[n-1] for every shot of the batch
+// -------------------------------------------------------------------------
+template <int FLAGS>
+__global__ __launch_bounds__(256) void k_forward(StepArgs a) {
+  __shared__ float lds_all[kWavesPerBlock][kWave + 2 * kRadius];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  int slot, tile;
+  if (!map_tile(a.d, a.S, a.xcd_map, wv, slot, tile)) return;
+  if (*a.err) return;
+  const SlotInfo si = a.slots[slot];
+  if (si.shot < 0) return;
+  const ShotDesc sd = a.shots[si.shot];
+  const int n = step_of(a);
+  if (n >= sd.nt - 1) return;
+
+  const Dims& d = a.d;
+  float* lds = lds_all[wv];
+  const int xt = tile % d.XT, zt = tile / d.XT;
+  const int xs0 = xt * kWave, xs = xs0 + lane, x = xs - d.off;
+  const bool xin = x >= 0 && x < d.X;
+  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
+  float* ubase = a.u + (int64_t)si.cs * 2 * d.field;
+  const float* ucur = ubase + (int64_t)(n & 1) * d.field;
+  float* unxt = ubase + (int64_t)((n + 1) & 1) * d.field;
+  const int hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
+  const bool hok = lane < 8 && hcol >= 0 && hcol < d.P;
+  const int dxs = max(max(d.N - x, x - (d.N + d.nx - 1)), 0);
+  const int mx = xs - d.mx0;
+
+  // source cell of this shot inside the tile?
+  const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
+  const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + n] : 0.0f;
+
+  int rp = 0, rend = 0, rz = INT_MAX;
+  if (FLAGS & kFwdRecord) {
+    const RmapDir dir = a.rdir[sd.rdir + xt];
+    rp = dir.begin;
+    rend = dir.begin + dir.count;
+    while (rp < rend && a.rrows[rp].z < z0) ++rp;
+    rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+  }
+  // snapshot pair k holds (u[a_k], u[a_k - 1]) with a_k = nt-1-kK, k >= 1
+  bool save = false;
+  float *snap0 = nullptr, *snap1 = nullptr, *strip = nullptr;
+  if (FLAGS & kFwdCkpt) {
+    const int rem = sd.nt - 2 - n;  // nt-1 - (n+1)
+    save = rem > 0 && (rem % sd.K) == 0;
+    if (save) {
+      const int k = rem / sd.K;
+      snap0 = a.snap + (int64_t)si.cs * a.snap_stride + (int64_t)(k - 1) * 2 * d.model;
+      snap1 = snap0 + d.model;
+    }
+    strip = a.strip + (int64_t)si.cs * a.strip_stride + (int64_t)(n + 1) * d.ring;
+  }
+  float* E = (FLAGS & kFwdIllum) ? a.E + (int64_t)slot * d.model : nullptr;
+
+  float wc[9], wh[9];
+  auto load_row = [&](int r, float& c, float& h) {
+    if (r >= 0 && r < d.Z) {
+      const float* row = ucur + (int64_t)r * d.P;
+      c = row[xs];
+      h = hok ? row[hcol] : 0.0f;
+    } else {
+      c = 0.0f;
+      h = 0.0f;
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < 8; ++j) load_row(z0 - 4 + j, wc[j], wh[j]);
+
+  for (int zb = z0; zb < z1; zb += 9) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int z = zb + r;
+      if (z >= z1) break;
+      load_row(z + 4, wc[(r + 8) % 9], wh[(r + 8) % 9]);
+      const float c = wc[(r + 4) % 9];
+      lds[kRadius + lane] = c;
+      if (lane < 4) lds[lane] = wh[(r + 4) % 9];
+      else if (lane < 8) lds[kWave + lane] = wh[(r + 4) % 9];
+      wave_lds_fence();
+      float lap = 0.0f;
+#pragma unroll
+      for (int k = 4; k >= 1; --k) {
+        const float sz = wc[(r + 4 - k) % 9] + wc[(r + 4 + k) % 9];
+        const float sx = lds[kRadius + lane - k] + lds[kRadius + lane + k];
+        lap = fmaf(ck(k), fmaf(-4.0f, c, sz + sx), lap);
+      }
+      wave_lds_fence();
+      if (src_tile && z == sd.src_z && xs == sd.src_xs) lap += fsrc;
+
+      const int64_t idx = (int64_t)z * d.P + xs;
+      float out = 0.0f;
+      int dd = 0;
+      if (xin) {
+        const float up = unxt[idx];
+        const float wv_ = a.w[idx];
+        const int dz = max(max(d.N - z, z - (d.N + d.nz - 1)), 0);
+        dd = max(dz, dxs);
+        if (dd == 0) {
+          out = fmaf(wv_, lap, 2.0f * c - up);
+          if (FLAGS & kFwdIllum) {
+            const float D = wv_ * lap;
+            const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
+            E[mi] = (n == 0) ? D * D : fmaf(D, D, E[mi]);
+          }
+        } else {
+          const double gm = a.sp_a * (double)(dd * dd);
+          out = (float)((2.0 * (double)c - (1.0 - gm) * (double)up + (double)wv_ * (double)lap) /
+                        (1.0 + gm));
+        }
+        unxt[idx] = out;
+        if (FLAGS & kFwdCkpt) {
+          const int ri = ring_index(d, z, x);
+          if (ri >= 0) strip[ri] = out;
+          if (save && dd == 0) {
+            const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
+            snap0[mi] = out;
+            snap1[mi] = c;
+          }
+        }
+      }
+      if (FLAGS & kFwdRecord) {
+        if (z == rz) {
+          const int tr = a.rmaps[a.rrows[rp].map + lane];
+          if (tr >= 0) a.traces[(int64_t)(n + 1) * a.ntrace + tr] = out;
+          ++rp;
+          rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// reverse step m (= nt-1-j for global reverse step j), fused:
+//   u[m-2] = 2u[m-1] - u[m] + w (L u[m-1] + f[m-1] e_src)   (model cells)
+//   strip ring of u[m-2] restored from the forward's boundary strips
+//   lam[m] = damped leapfrog of lam[m+1], lam[m+2] + w psi'[m] at receivers
+//   g += lam[m] D[m],  E += D[m]^2,  D[m] = w (L u[m-1] + f[m-1] e_src)
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
+  __shared__ float ldsU_all[kWavesPerBlock][kWave + 2 * kRadius];
+  __shared__ float ldsL_all[kWavesPerBlock][kWave + 2 * kRadius];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  int slot, tile;
+  if (!map_tile(a.d, a.S, a.xcd_map, wv, slot, tile)) return;
+  if (*a.err) return;
+  const SlotInfo si = a.slots[slot];
+  if (si.shot < 0) return;
+  const ShotDesc sd = a.shots[si.shot];
+  const int m = sd.nt - 1 - step_of(a);
+  if (m < 1) return;
+
+  const Dims& d = a.d;
+  float* ldsU = ldsU_all[wv];
+  float* ldsL = ldsL_all[wv];
+  const int xt = tile % d.XT, zt = tile / d.XT;
+  const int xs0 = xt * kWave, xs = xs0 + lane, x = xs - d.off;
+  const bool xin = x >= 0 && x < d.X;
+  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
+  float* ubase = a.u + (int64_t)si.cs * 2 * d.field;
+  float* u_m = ubase + (int64_t)(m & 1) * d.field;          // u[m] in, u[m-2] out
+  const float* u_m1 = ubase + (int64_t)((m - 1) & 1) * d.field;
+  float* lbase = a.lam + (int64_t)slot * 2 * d.field;
+  const float* l_p1 = lbase + (int64_t)((m + 1) & 1) * d.field;  // lam[m+1]
+  float* l_p2 = lbase + (int64_t)(m & 1) * d.field;              // lam[m+2] in, lam[m] out
+  const int hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
+  const bool hok = lane < 8 && hcol >= 0 && hcol < d.P;
+  const int dxs = max(max(d.N - x, x - (d.N + d.nx - 1)), 0);
+  const int mx = xs - d.mx0;
+  const int hmx = hcol - d.mx0;
+  const bool mcol = mx >= 0 && mx < d.nx;
+  const bool hmcol = hmx >= 0 && hmx < d.nx;
+
+  // snapshot reset: at m == a_k the model cells of u[m] and u[m-1] come from
+  // snapshot k, and at m == a_k - 1 u[m] comes from it again, so that both
+  // levels of the recursion restart from forward values (a reconstructed
+  // level paired with an exact one would act as a velocity kick that grows)
+  const int rem = sd.nt - 1 - m;
+  const bool reset = rem > 0 && (rem % sd.K) == 0 && rem / sd.K <= sd.nsnap;
+  const bool reset_prev = rem > 1 && ((rem - 1) % sd.K) == 0 && (rem - 1) / sd.K <= sd.nsnap;
+  const float* ckpt = a.snap + (int64_t)si.cs * a.snap_stride;
+  const float* snap0 = reset ? ckpt + (int64_t)(rem / sd.K - 1) * 2 * d.model : nullptr;
+  const float* snap1 = reset ? snap0 + d.model : nullptr;
+  const float* snapp = reset_prev ? ckpt + (int64_t)((rem - 1) / sd.K - 1) * 2 * d.model + d.model : nullptr;
+  const float* strip = (m >= 3) ? a.strip + (int64_t)si.cs * a.strip_stride + (int64_t)(m - 2) * d.ring
+                                : nullptr;
+  const bool first = (m == sd.nt - 1);
+  float* G = a.g + (int64_t)slot * d.model;
+  float* E = a.E + (int64_t)slot * d.model;
+
+  const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
+  const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 1)] : 0.0f;
+
+  int rp, rend, rz;
+  {
+    const RmapDir dir = a.rdir[sd.rdir + xt];
+    rp = dir.begin;
+    rend = dir.begin + dir.count;
+    while (rp < rend && a.rrows[rp].z < z0) ++rp;
+    rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+  }
+  const float* psi = a.traces + (int64_t)m * a.ntrace;
+
+  const int uz_lo = d.N - kRadius, uz_hi = d.N + d.nz + kRadius;  // rows where u is defined
+  float uc[9], uh[9], lc[9], lh[9];
+  auto load_rows = [&](int r, float& cu, float& hu, float& cl, float& hl) {
+    if (r >= 0 && r < d.Z) {
+      const int64_t ro = (int64_t)r * d.P;
+      cl = l_p1[ro + xs];
+      hl = hok ? l_p1[ro + hcol] : 0.0f;
+      if (r >= uz_lo && r < uz_hi) {
+        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
+        const int64_t mo = (int64_t)(r - d.N) * d.nx;
+        cu = (mrow && mcol) ? snap1[mo + mx] : u_m1[ro + xs];
+        hu = hok ? ((mrow && hmcol) ? snap1[mo + hmx] : u_m1[ro + hcol]) : 0.0f;
+      } else {
+        cu = 0.0f;
+        hu = 0.0f;
+      }
+    } else {
+      cu = hu = cl = hl = 0.0f;
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < 8; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+
+  for (int zb = z0; zb < z1; zb += 9) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int z = zb + r;
+      if (z >= z1) break;
+      const int s8 = (r + 8) % 9, s4 = (r + 4) % 9;
+      load_rows(z + 4, uc[s8], uh[s8], lc[s8], lh[s8]);
+      const float cu = uc[s4], cl = lc[s4];
+      ldsU[kRadius + lane] = cu;
+      ldsL[kRadius + lane] = cl;
+      if (lane < 4) {
+        ldsU[lane] = uh[s4];
+        ldsL[lane] = lh[s4];
+      } else if (lane < 8) {
+        ldsU[kWave + lane] = uh[s4];
+        ldsL[kWave + lane] = lh[s4];
+      }
+      wave_lds_fence();
+      float lapL = 0.0f;
+#pragma unroll
+      for (int k = 4; k >= 1; --k) {
+        const float sz = lc[(r + 4 - k) % 9] + lc[(r + 4 + k) % 9];
+        const float sx = ldsL[kRadius + lane - k] + ldsL[kRadius + lane + k];
+        lapL = fmaf(ck(k), fmaf(-4.0f, cl, sz + sx), lapL);
+      }
+      const bool mrow = z >= d.N && z < d.N + d.nz;
+      float lapU = 0.0f;
+      if (mrow) {
+#pragma unroll
+        for (int k = 4; k >= 1; --k) {
+          const float sz = uc[(r + 4 - k) % 9] + uc[(r + 4 + k) % 9];
+          const float sx = ldsU[kRadius + lane - k] + ldsU[kRadius + lane + k];
+          lapU = fmaf(ck(k), fmaf(-4.0f, cu, sz + sx), lapU);
+        }
+      }
+      wave_lds_fence();
+      int tr = -1;
+      if (z == rz) {
+        tr = a.rmaps[a.rrows[rp].map + lane];
+        ++rp;
+        rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+      }
+      if (tr >= 0) lapL += psi[tr];
+      if (src_tile && z == sd.src_z && xs == sd.src_xs) lapU += fsrc;
+
+      if (xin) {
+        const int64_t idx = (int64_t)z * d.P + xs;
+        const float wv_ = a.w[idx];
+        const float l2 = l_p2[idx];
+        const int dz = max(max(d.N - z, z - (d.N + d.nz - 1)), 0);
+        const int dd = max(dz, dxs);
+        float lout;
+        if (dd == 0) {
+          lout = fmaf(wv_, lapL, 2.0f * cl - l2);
+        } else {
+          const double gm = a.sp_a * (double)(dd * dd);
+          lout = (float)((2.0 * (double)cl - (1.0 - gm) * (double)l2 + (double)wv_ * (double)lapL) /
+                         (1.0 + gm));
+        }
+        l_p2[idx] = lout;
+        if (dd == 0) {
+          const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
+          const float u0 = reset ? snap0[mi] : (reset_prev ? snapp[mi] : u_m[idx]);
+          const float D = wv_ * lapU;
+          u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - u0);
+          G[mi] = fmaf(lout, D, G[mi]);
+          E[mi] = first ? D * D : fmaf(D, D, E[mi]);
+        } else {
+          const int ri = ring_index(d, z, x);
+          if (ri >= 0) u_m[idx] = strip ? strip[ri] : 0.0f;
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// small kernels
+// -------------------------------------------------------------------------
+__global__ void k_prep(Dims d, const float* __restrict__ v, float* __restrict__ w, double dt2_h2,
+                       float vmax, int32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.field) return;
+  const int z = (int)(i / d.P), xs = (int)(i % d.P), x = xs - d.off;
+  float out = 0.0f;
+  if (x >= 0 && x < d.X) {
+    const int iz = min(max(z - d.N, 0), d.nz - 1), ix = min(max(x - d.N, 0), d.nx - 1);
+    const float vv = v[(int64_t)iz * d.nx + ix];
+    if (!(vv > 0.0f && vv <= vmax)) atomicOr(err, 1);
+    out = (float)(dt2_h2 * (double)vv * (double)vv);
+  }
+  w[i] = out;
+}
+
+__global__ void k_fill(uint32_t* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = i; k < n; k += stride) p[k] = 0u;
+}
+
+__global__ void k_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,
+                             int use_cs) {
+  const SlotInfo si = slots[blockIdx.y];
+  if (si.shot < 0) return;
+  float* p = base + (int64_t)(use_cs ? si.cs : (int)blockIdx.y) * stride;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = 0.0f;
+}
+
+__global__ void k_advance(int32_t* ctr, int32_t by) { *ctr += by; }
+__global__ void k_set(int32_t* ctr, int32_t value) { *ctr = value; }
+
+// misfit of one trace per thread; psi' = psi * h^2/dt^2 written in place
+__global__ void k_misfit(MisfitArgs a) {
+  const SlotInfo si = a.slots[blockIdx.y];
+  if (si.shot < 0 || *a.err) return;
+  const ShotDesc sd = a.shots[si.shot];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= sd.nrec) return;
+  const int tr = sd.rec_begin + r;
+  float* syn = a.traces + tr;
+  const float* obs = a.dobs + (int64_t)tr * a.nt_max;
+  const int64_t st = a.ntrace;
+  const int nt = sd.nt;
+  double J = 0.0;
+  if (a.kind == 0) {
+    for (int t = 0; t < nt; ++t) {
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      J += rr * rr;
+      syn[t * st] = (float)(rr * a.psi_scale);
+    }
+  } else {
+    // eq. (2): R[n] = dt sum_{k<=n} r[k]; psi[n] = dt sum_{k>=n} R[k] = dt (S - sum_{k<n} R[k])
+    double R = 0.0, S = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      R += a.dt * rr;
+      J += R * R;
+      S += R;
+    }
+    double Rp = 0.0, Pn = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      Rp += a.dt * rr;
+      syn[t * st] = (float)(a.dt * (S - Pn) * a.psi_scale);
+      Pn += Rp;
+    }
+  }
+  a.Jpart[tr] = 0.5 * J;
+}
+
+// deterministic fixed-order sum of per-trace misfits
+__global__ __launch_bounds__(1024) void k_reduce_J(const double* part, int n, double* J,
+                                                   const int32_t* err) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = (*err) ? NAN : sh[0];
+}
+
+// per-batch Hessian epilogue over model rows: H1 += E_s/dt^3 and
+// D(x,h) += (4/v^6) E_s(x+h)/dt^3 A_s(x-h).  A_s and E_s of each shot are
+// staged in LDS for the tile plus HM cells on each side, so every asinh pair
+// is evaluated once per cell and shot; HM is the compile-time offset bound.
+constexpr int kEpiTile = 256;
+template <int HM>
+__global__ __launch_bounds__(kEpiTile) void k_epilogue(EpiArgs a) {
+  __shared__ float shE[kEpiTile + 2 * HM];
+  __shared__ float shA[kEpiTile + 2 * HM];
+  const Dims& d = a.d;
+  const int iz = blockIdx.y;
+  const int x0 = blockIdx.x * kEpiTile;
+  const int ix = x0 + threadIdx.x;
+  const bool in = ix < d.nx;
+  const int H = a.hmax;
+  const int64_t cell = (int64_t)iz * d.nx + ix;
+  float h1 = 0.0f;
+  float acc[2 * HM + 1];
+#pragma unroll
+  for (int h = 0; h < 2 * HM + 1; ++h) acc[h] = 0.0f;
+  const bool bad = *a.err != 0;
+  for (int s = 0; s < a.S && !bad; ++s) {
+    const SlotInfo si = a.slots[s];
+    if (si.shot < 0) continue;
+    const float* Es = a.E + (int64_t)s * d.model + (int64_t)iz * d.nx;
+    if (a.H1 && in) h1 += Es[ix] * a.inv_dt3;
+    if (!a.D) continue;
+    const ShotDesc sd = a.shots[si.shot];
+    const float zm = fmaxf((float)(iz - sd.rec_z0) * a.h, 0.5f * a.h);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kEpiTile + 2 * HM; j += kEpiTile) {
+      const int xx = x0 - HM + j;
+      float e = 0.0f, A = 0.0f;
+      if (xx >= 0 && xx < d.nx) {
+        e = Es[xx] * a.inv_dt3;
+        if (a.rcv_none) {
+          A = 1.0f;
+        } else {
+          const float xm = (float)xx * a.h;
+          A = asinhf((sd.xmax_m - xm) / zm) - asinhf((sd.xmin_m - xm) / zm);
+        }
+      }
+      shE[j] = e;
+      shA[j] = A;
+    }
+    __syncthreads();
+    // slice h: E at x+h (LDS index tid + HM + h), A at x-h (tid + HM - h)
+#pragma unroll
+    for (int h = -HM; h <= HM; ++h)
+      if (h >= -H && h <= H)
+        acc[h + HM] = fmaf(shE[threadIdx.x + HM + h], shA[threadIdx.x + HM - h], acc[h + HM]);
+  }
+  if (!in || bad) return;
+  if (a.H1) a.H1[cell] += h1;
+  if (a.D) {
+    const float vv = a.v[cell];
+    const float v2 = vv * vv;
+    const float fac = 4.0f / (v2 * v2 * v2);
+#pragma unroll
+    for (int h = -HM; h <= HM; ++h)
+      if (h >= -H && h <= H) a.D[(int64_t)(h + H) * d.model + cell] += fac * acc[h + HM];
+  }
+}
+
+__global__ void k_gradient_out(Dims d, const float* gacc, int S, const float* v, const double* scale,
+                               float* grad, const int32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.model) return;
+  float s = 0.0f;
+  for (int k = 0; k < S; ++k) s += gacc[(int64_t)k * d.model + i];
+  const double vv = v[i];
+  const double sc = scale ? *scale : 1.0;
+  grad[i] = (*err) ? NAN : (float)(sc * 2.0 / (vv * vv * vv) * (double)s);
+}
+
+__global__ void k_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
+                             const int32_t* trace_shot, float* data) {
+  const int tr = blockIdx.x;
+  const int nt = shots[trace_shot[tr]].nt;
+  for (int t = threadIdx.x; t < nt_max; t += blockDim.x)
+    data[(int64_t)tr * nt_max + t] = (t >= 1 && t < nt) ? traces[(int64_t)t * ntrace + tr] : 0.0f;
+}
+
+__global__ void k_precond_p(int64_t n, const float* v, int kind, const float* hdiag, int nh,
+                            float* out, uint32_t* maxbits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float p = 0.0f;
+  if (i < n) {
+    if (kind == 0) {
+      const double vv = v[i];
+      p = (float)(4.0 / (vv * vv * vv * vv * vv * vv) * (double)hdiag[i]);
+    } else {
+      for (int h = 0; h < nh; ++h) p += hdiag[(int64_t)h * n + i];
+    }
+    out[i] = p;
+  }
+  // non-negative floats order like their bit patterns
+  __shared__ uint32_t m;
+  if (threadIdx.x == 0) m = 0u;
+  __syncthreads();
+  atomicMax(&m, __float_as_uint(fmaxf(p, 0.0f)));
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(maxbits, m);
+}
+
+__global__ void k_precond_apply(int64_t n, const float* grad, float eps, const uint32_t* maxbits,
+                                float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float wl = eps * __uint_as_float(*maxbits);
+  out[i] = grad[i] / (out[i] + wl);
+}
+
+// -------------------------------------------------------------------------
+// launchers
+// -------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+static inline unsigned step_blocks(const Dims& d, int S) {
+  const int T = d.XT * d.ZT;
+  const int bps = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+  return (unsigned)(bps * S);
+}
+
+hipError_t launch_prep(const Dims& d, const float* v, float* w, float dt, float h, float vmax,
+                       int32_t* err, hipStream_t s) {
+  const double dt2_h2 = (double)dt * (double)dt / ((double)h * (double)h);
+  hipLaunchKernelGGL(k_prep, dim3(blocks_for(d.field, 256)), dim3(256), 0, s, d, v, w, dt2_h2, vmax,
+                     err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s) {
+  const size_t n = nbytes / 4;
+  if (n == 0) return hipSuccess;
+  const unsigned b = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill, dim3(b), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,
+                             int S, int use_cs, hipStream_t s) {
+  if (S <= 0 || count <= 0) return hipSuccess;
+  const unsigned bx = (unsigned)std::min<int64_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_slots, dim3(bx, S), dim3(256), 0, s, base, stride, count, slots, use_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const StepArgs& a, int flags, hipStream_t s) {
+  const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  switch (flags) {
+    case 0: hipLaunchKernelGGL(k_forward<0>, grid, block, 0, s, a); break;
+    case kFwdRecord: hipLaunchKernelGGL(k_forward<kFwdRecord>, grid, block, 0, s, a); break;
+    case kFwdRecord | kFwdCkpt:
+      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt>), grid, block, 0, s, a);
+      break;
+    case kFwdIllum: hipLaunchKernelGGL(k_forward<kFwdIllum>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reverse, dim3(step_blocks(a.d, a.S)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, ctr, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, s, ctr, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_misfit(const MisfitArgs& a, int S, int max_nrec, hipStream_t s) {
+  if (S <= 0 || max_nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_misfit, dim3(blocks_for(max_nrec, 64), S), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_J(const double* part, int n, double* J, const int32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_J, dim3(1), dim3(1024), 0, s, part, n, J, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s) {
+  const dim3 grid(blocks_for(a.d.nx, kEpiTile), a.d.nz), block(kEpiTile);
+  if (a.hmax <= 4) hipLaunchKernelGGL(k_epilogue<4>, grid, block, 0, s, a);
+  else if (a.hmax <= 16) hipLaunchKernelGGL(k_epilogue<16>, grid, block, 0, s, a);
+  else if (a.hmax <= 64) hipLaunchKernelGGL(k_epilogue<64>, grid, block, 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const float* v,
+                               const double* scale, float* grad, const int32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_gradient_out, dim3(blocks_for(d.model, 256)), dim3(256), 0, s, d, gacc, S, v,
+                     scale, grad, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
+                             const int32_t* trace_shot, float* data, hipStream_t s) {
+  if (ntrace <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_traces_out, dim3(ntrace), dim3(256), 0, s, traces, ntrace, nt_max, shots,
+                     trace_shot, data);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int kind,
+                          const float* hdiag, int hmax, float eps, float* out, uint32_t* maxbits,
+                          hipStream_t s) {
+  const int64_t n = (int64_t)nz * nx;
+  hipError_t e = launch_fill(maxbits, 4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_precond_p, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, v, kind, hdiag,
+                     2 * hmax + 1, out, maxbits);
+  hipLaunchKernelGGL(k_precond_apply, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, grad, eps,
+                     maxbits, out);
+  return hipGetLastError();
+}
+
+}  // namespace fwi

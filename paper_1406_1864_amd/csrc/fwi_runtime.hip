@@ -1,0 +1,910 @@
+// Host runtime of libfwi: validation, execution plans, workspace layout,
+// batched time loops (direct launches or replayed hipGraph chunks), the
+// autotuner and the C ABI of include/fwi.h.
+//
+// A plan fixes everything that depends only on the grid, the acquisition
+// geometry and the execution settings: padded storage layout, the shot ->
+// batch/slot schedule (shots sorted by record length, longest first), the
+// per-shot descriptors (record length, snapshot spacing K = ceil(sqrt(nt)),
+// source cell, receiver range, aperture), the receiver tile maps and the
+// byte layout of the caller's workspace.  Plans are cached by a hash of
+// those inputs; captured graphs are cached inside their plan, keyed by the
+// device pointers they bake in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fwi.h"
+#include "fwi_internal.h"
+
+namespace fwi {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(FWI_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- hashing
+struct Hasher {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  }
+  template <class T>
+  void pod(const T& v) { bytes(&v, sizeof(T)); }
+};
+
+// ---------------------------------------------------------------- validation
+int check_inputs(const fwi_grid* g, const fwi_geometry* geo) {
+  if (!g || !geo) return fail(FWI_ERR_ARG, "grid and geometry must not be NULL");
+  if (g->nz < 1 || g->nx < 1) return fail(FWI_ERR_ARG, "nz and nx must be >= 1");
+  if (g->nz > 65535) return fail(FWI_ERR_ARG, "nz must be <= 65535");
+  if (!(g->dx > 0.0f) || !(g->dt > 0.0f) || !std::isfinite(g->dx) || !std::isfinite(g->dt))
+    return fail(FWI_ERR_ARG, "dx and dt must be positive and finite");
+  if (g->nt_max < 2) return fail(FWI_ERR_ARG, "nt_max must be >= 2");
+  if (g->nsponge < kRadius) return fail(FWI_ERR_ARG, "nsponge must be >= 4");
+  if (!(g->v_ref > 0.0f) || !std::isfinite(g->v_ref)) return fail(FWI_ERR_ARG, "v_ref must be positive");
+  const double courant = (double)g->v_ref * g->dt / g->dx;
+  if (courant > FWI_CFL_LIMIT)
+    return fail(FWI_ERR_CFL, "v_ref*dt/dx = " + std::to_string(courant) + " exceeds the stability bound " +
+                                 std::to_string(FWI_CFL_LIMIT));
+  if (geo->nshot < 0) return fail(FWI_ERR_ARG, "nshot must be >= 0");
+  if (geo->nshot == 0) return FWI_OK;
+  if (!geo->src_iz || !geo->src_ix || !geo->rec_ptr)
+    return fail(FWI_ERR_ARG, "src_iz, src_ix and rec_ptr must not be NULL");
+  if (geo->rec_ptr[0] != 0) return fail(FWI_ERR_GEOM, "rec_ptr[0] must be 0");
+  for (int s = 0; s < geo->nshot; ++s) {
+    if (geo->rec_ptr[s + 1] < geo->rec_ptr[s]) return fail(FWI_ERR_GEOM, "rec_ptr must be non-decreasing");
+    if (geo->src_iz[s] < 0 || geo->src_iz[s] >= g->nz || geo->src_ix[s] < 0 || geo->src_ix[s] >= g->nx)
+      return fail(FWI_ERR_GEOM, "source of shot " + std::to_string(s) + " lies outside the model");
+    const int nt = geo->nt ? geo->nt[s] : g->nt_max;
+    if (nt < 2 || nt > g->nt_max)
+      return fail(FWI_ERR_GEOM, "nt of shot " + std::to_string(s) + " outside [2, nt_max]");
+  }
+  const int ntr = geo->rec_ptr[geo->nshot];
+  if (ntr > 0 && (!geo->rec_iz || !geo->rec_ix)) return fail(FWI_ERR_ARG, "rec_iz/rec_ix must not be NULL");
+  std::vector<int64_t> cells;
+  for (int s = 0; s < geo->nshot; ++s) {
+    cells.clear();
+    for (int r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
+      if (geo->rec_iz[r] < 0 || geo->rec_iz[r] >= g->nz || geo->rec_ix[r] < 0 || geo->rec_ix[r] >= g->nx)
+        return fail(FWI_ERR_GEOM, "receiver " + std::to_string(r) + " lies outside the model");
+      cells.push_back((int64_t)geo->rec_iz[r] * g->nx + geo->rec_ix[r]);
+    }
+    std::sort(cells.begin(), cells.end());
+    if (std::adjacent_find(cells.begin(), cells.end()) != cells.end())
+      return fail(FWI_ERR_GEOM, "shot " + std::to_string(s) + " has two receivers on one cell");
+  }
+  return FWI_OK;
+}
+
+// ---------------------------------------------------------------- plan
+enum Phase { kPhaseFwd = 0, kPhaseRev = 1 };
+
+struct Layout {
+  size_t hdr, shots, slots, rdir, rrows, rmaps, trace_shot;
+  size_t w, traces, jpart, u, lam, g, E, snap, strip, total;
+};
+
+// device header at the start of every workspace
+struct Header {
+  int32_t err;       // device error flag
+  int32_t step;      // step counter of replayed graph chunks
+  uint32_t maxbits;  // preconditioner max reduction
+  int32_t pad[61];
+};
+
+struct Plan {
+  uint64_t key = 0;
+  uint64_t ikey = 0;  // hash of grid + geometry
+  Dims d{};
+  int nshot = 0, ntrace = 0, max_nrec = 0, nt_max = 0;
+  int S = 1, nbatch = 0, ncs = 0;
+  int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
+  double sp_a = 0.0;
+  float dx = 0, dt = 0;
+  std::vector<ShotDesc> shots;
+  std::vector<SlotInfo> slots;  // [nbatch][S]
+  std::vector<int> batch_nt;    // longest record of each batch
+  std::vector<RmapDir> rdir;
+  std::vector<RmapRow> rrows;
+  std::vector<int32_t> rmaps;
+  std::vector<int32_t> trace_shot;
+  int64_t snap_stride = 0, strip_stride = 0;
+  Layout L{};
+  std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+  // split-mode state: workspace, v and wavelet of the last fwi_misfit_forward
+  const void* fwd_ws = nullptr;
+  const void* fwd_v = nullptr;
+  const void* fwd_wavelet = nullptr;
+  ~Plan() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  }
+};
+
+struct ExecChoice {
+  int S, TZ, graph_steps;
+};
+
+std::mutex g_mutex;
+std::list<std::shared_ptr<Plan>> g_plans;  // most recent first
+std::map<std::vector<uint64_t>, ExecChoice> g_tuned;
+hipStream_t g_capture_stream = nullptr;
+
+int shot_nt(const fwi_grid* g, const fwi_geometry* geo, int s) { return geo->nt ? geo->nt[s] : g->nt_max; }
+
+uint64_t inputs_hash(const fwi_grid* g, const fwi_geometry* geo) {
+  Hasher h;
+  h.pod(*g);
+  h.pod(geo->nshot);
+  if (geo->nshot > 0) {
+    h.bytes(geo->src_iz, sizeof(int32_t) * geo->nshot);
+    h.bytes(geo->src_ix, sizeof(int32_t) * geo->nshot);
+    h.bytes(geo->rec_ptr, sizeof(int32_t) * (geo->nshot + 1));
+    const int ntr = geo->rec_ptr[geo->nshot];
+    if (ntr > 0) {
+      h.bytes(geo->rec_iz, sizeof(int32_t) * ntr);
+      h.bytes(geo->rec_ix, sizeof(int32_t) * ntr);
+    }
+    for (int s = 0; s < geo->nshot; ++s) h.pod(shot_nt(g, geo, s));
+  }
+  return h.h;
+}
+
+int default_tile_rows(int Z) {
+  // long sweeps amortise the 8-row z halo; keep >= 4 tiles per column for
+  // parallelism on small grids
+  int tz = 64;
+  while (tz > 16 && (Z + tz - 1) / tz < 4) tz /= 2;
+  return tz;
+}
+
+int default_shots_in_flight(int nshot) {
+  int S = std::min(nshot, 32);
+  if (S >= 8) S -= S % 8;
+  return std::max(S, 1);
+}
+
+void build_dims(Plan& p, const fwi_grid* g, int TZ) {
+  Dims& d = p.d;
+  d.nz = g->nz;
+  d.nx = g->nx;
+  d.N = g->nsponge;
+  d.Z = d.nz + 2 * d.N;
+  d.X = d.nx + 2 * d.N;
+  d.off = (kWave - d.N % kWave) % kWave;
+  d.mx0 = d.off + d.N;
+  d.P = (int)align_up(d.off + d.X, kWave);
+  d.XT = d.P / kWave;
+  d.TZ = TZ;
+  d.ZT = (d.Z + TZ - 1) / TZ;
+  d.ring = 8 * (d.nx + d.nz);
+  d.field = (int64_t)d.Z * d.P;
+  d.model = (int64_t)d.nz * d.nx;
+}
+
+// what: FWI_WS_FORWARD / GRADIENT / HESSIAN / AUTOGRAD
+std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, const ExecChoice& ex,
+                                 int plain, int what, uint64_t key) {
+  auto p = std::make_shared<Plan>();
+  p->key = key;
+  p->what = what;
+  p->plain = plain;
+  p->split = (what == FWI_WS_AUTOGRAD);
+  p->nshot = geo->nshot;
+  p->nt_max = g->nt_max;
+  p->dx = g->dx;
+  p->dt = g->dt;
+  p->S = plain ? 1 : std::max(1, std::min(ex.S, std::max(geo->nshot, 1)));
+  p->graph_steps = plain ? -1 : ex.graph_steps;
+  p->xcd_map = (p->S >= 8 && p->S % 8 == 0) ? 1 : 0;
+  build_dims(*p, g, ex.TZ);
+  const Dims& d = p->d;
+  const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
+  p->sp_a = 0.5 * g->dt * eta_max / ((double)d.N * d.N);
+
+  const int ns = geo->nshot;
+  p->ntrace = ns > 0 ? geo->rec_ptr[ns] : 0;
+  p->trace_shot.assign(std::max(p->ntrace, 1), 0);
+  p->shots.resize(std::max(ns, 1));
+  int max_nsnap = 0;
+  for (int s = 0; s < ns; ++s) {
+    ShotDesc& sd = p->shots[s];
+    std::memset(&sd, 0, sizeof(sd));
+    sd.nt = shot_nt(g, geo, s);
+    sd.K = std::max(1, (int)std::ceil(std::sqrt((double)sd.nt)));
+    sd.nsnap = (sd.nt - 2) / sd.K;
+    max_nsnap = std::max(max_nsnap, sd.nsnap);
+    sd.src_z = geo->src_iz[s] + d.N;
+    sd.src_xs = geo->src_ix[s] + d.mx0;
+    sd.rec_begin = geo->rec_ptr[s];
+    sd.nrec = geo->rec_ptr[s + 1] - geo->rec_ptr[s];
+    p->max_nrec = std::max(p->max_nrec, sd.nrec);
+    sd.rdir = s * d.XT;
+    int zmin = g->nz, xmin = g->nx, xmax = -1;
+    for (int r = sd.rec_begin; r < sd.rec_begin + sd.nrec; ++r) {
+      zmin = std::min(zmin, geo->rec_iz[r]);
+      xmin = std::min(xmin, geo->rec_ix[r]);
+      xmax = std::max(xmax, geo->rec_ix[r]);
+      p->trace_shot[r] = s;
+    }
+    sd.rec_z0 = sd.nrec ? zmin : 0;
+    sd.xmin_m = sd.nrec ? (float)((double)xmin * g->dx) : 0.0f;
+    sd.xmax_m = sd.nrec ? (float)((double)xmax * g->dx) : 0.0f;
+  }
+  // receiver tile maps: for each (shot, x tile) the rows holding receivers,
+  // each with a 64-entry lane -> trace map
+  p->rdir.assign((size_t)std::max(ns, 1) * d.XT, RmapDir{0, 0});
+  for (int s = 0; s < ns; ++s) {
+    std::map<std::pair<int, int>, std::vector<int>> rows;  // (xt, z) -> traces
+    for (int r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) rows[{(geo->rec_ix[r] + d.mx0) / kWave, geo->rec_iz[r] + d.N}].push_back(r);
+    for (auto& kv : rows) {
+      const int xt = kv.first.first, z = kv.first.second;
+      RmapDir& dir = p->rdir[(size_t)s * d.XT + xt];
+      if (dir.count == 0) dir.begin = (int)p->rrows.size();
+      dir.count++;
+      const int map = (int)p->rmaps.size();
+      p->rrows.push_back(RmapRow{z, map});
+      p->rmaps.resize(map + kWave, -1);
+      for (int r : kv.second) p->rmaps[map + (geo->rec_ix[r] + d.mx0) % kWave] = r;
+    }
+  }
+  if (p->rrows.empty()) p->rrows.push_back(RmapRow{0, 0});
+  if (p->rmaps.empty()) p->rmaps.assign(kWave, -1);
+
+  // batches: longest records first so that a batch's shots end together
+  std::vector<int> order(ns);
+  for (int s = 0; s < ns; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->shots[a].nt > p->shots[b].nt; });
+  p->nbatch = (ns + p->S - 1) / p->S;
+  p->slots.assign((size_t)std::max(p->nbatch, 1) * p->S, SlotInfo{-1, 0});
+  p->batch_nt.assign(std::max(p->nbatch, 1), 0);
+  for (int i = 0; i < ns; ++i) {
+    const int b = i / p->S, s = i % p->S, shot = order[i];
+    p->slots[(size_t)b * p->S + s] = SlotInfo{shot, p->split ? shot : s};
+    p->batch_nt[b] = std::max(p->batch_nt[b], p->shots[shot].nt);
+  }
+  p->ncs = p->split ? std::max(ns, 1) : p->S;
+
+  // workspace layout
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD);
+  const bool hess = (what == FWI_WS_HESSIAN);
+  Layout& L = p->L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + std::max(bytes, (size_t)4));
+    return at;
+  };
+  L.hdr = take(sizeof(Header));
+  L.shots = take(sizeof(ShotDesc) * p->shots.size());
+  L.slots = take(sizeof(SlotInfo) * p->slots.size());
+  L.rdir = take(sizeof(RmapDir) * p->rdir.size());
+  L.rrows = take(sizeof(RmapRow) * p->rrows.size());
+  L.rmaps = take(sizeof(int32_t) * p->rmaps.size());
+  L.trace_shot = take(sizeof(int32_t) * p->trace_shot.size());
+  L.w = take(sizeof(float) * d.field);
+  L.traces = take(sizeof(float) * (size_t)g->nt_max * std::max(p->ntrace, 1));
+  L.jpart = take(sizeof(double) * std::max(p->ntrace, 1));
+  L.u = take(sizeof(float) * 2 * d.field * p->ncs);
+  L.lam = grad ? take(sizeof(float) * 2 * d.field * p->S) : o;
+  L.g = grad ? take(sizeof(float) * d.model * p->S) : o;
+  L.E = (grad || hess) ? take(sizeof(float) * d.model * p->S) : o;
+  p->snap_stride = grad ? (int64_t)max_nsnap * 2 * d.model : 0;
+  p->strip_stride = grad ? (int64_t)g->nt_max * d.ring : 0;
+  L.snap = grad ? take(sizeof(float) * p->snap_stride * p->ncs) : o;
+  L.strip = grad ? take(sizeof(float) * p->strip_stride * p->ncs) : o;
+  L.total = o;
+  return p;
+}
+
+template <class T>
+T* at(void* ws, size_t off) { return (T*)((char*)ws + off); }
+
+StepArgs step_args(const Plan& p, void* ws, int batch, const float* wavelet, int64_t wstride) {
+  StepArgs a{};
+  a.d = p.d;
+  a.S = p.S;
+  a.xcd_map = p.xcd_map;
+  a.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
+  a.shots = at<ShotDesc>(ws, p.L.shots);
+  a.rdir = at<RmapDir>(ws, p.L.rdir);
+  a.rrows = at<RmapRow>(ws, p.L.rrows);
+  a.rmaps = at<int32_t>(ws, p.L.rmaps);
+  a.w = at<float>(ws, p.L.w);
+  a.u = at<float>(ws, p.L.u);
+  a.lam = at<float>(ws, p.L.lam);
+  a.g = at<float>(ws, p.L.g);
+  a.E = at<float>(ws, p.L.E);
+  a.traces = at<float>(ws, p.L.traces);
+  a.ntrace = std::max(p.ntrace, 1);
+  a.wavelet = wavelet;
+  a.wstride = wstride;
+  a.snap = at<float>(ws, p.L.snap);
+  a.strip = at<float>(ws, p.L.strip);
+  a.snap_stride = p.snap_stride;
+  a.strip_stride = p.strip_stride;
+  a.sp_a = p.sp_a;
+  a.step_ctr = nullptr;
+  a.step = 0;
+  a.err = &at<Header>(ws, p.L.hdr)->err;
+  return a;
+}
+
+hipError_t get_capture_stream(hipStream_t* out) {
+  if (!g_capture_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = g_capture_stream;
+  return hipSuccess;
+}
+
+// Run `nsteps` time steps of one phase for one batch: direct launches, or
+// replays of a captured chunk of `graph_steps` launches that read the step
+// base from the workspace header.
+int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, const float* wavelet,
+              int64_t wstride, hipStream_t stream) {
+  if (nsteps <= 0) return FWI_OK;
+  StepArgs a = step_args(p, ws, batch, wavelet, wstride);
+  auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
+    return phase == kPhaseFwd ? launch_forward(args, flags, s) : launch_reverse(args, s);
+  };
+  const int T = p.graph_steps;
+  if (T <= 0) {
+    for (int k = 0; k < nsteps; ++k) {
+      a.step = k;
+      HIP_TRY(launch(a, stream));
+    }
+    return FWI_OK;
+  }
+  int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
+  const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
+                                      (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
+                                      (uint64_t)wstride};
+  hipGraphExec_t exec = nullptr;
+  auto it = p.graphs.find(gkey);
+  if (it != p.graphs.end()) {
+    exec = it->second;
+  } else {
+    hipStream_t cs;
+    HIP_TRY(get_capture_stream(&cs));
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    a.step_ctr = ctr;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < T && le == hipSuccess; ++k) {
+      a.step = k;
+      le = launch(a, cs);
+    }
+    if (le == hipSuccess) le = launch_advance(ctr, T, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return fail(FWI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(le));
+    }
+    if (ee != hipSuccess) return fail(FWI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(FWI_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    p.graphs[gkey] = exec;
+  }
+  // whole chunks as graph replays, the remainder as direct launches, so that
+  // every launch advances at least one shot
+  const int full = nsteps / T;
+  if (full > 0) {
+    HIP_TRY(launch_set(ctr, 0, stream));
+    for (int c = 0; c < full; ++c) HIP_TRY(hipGraphLaunch(exec, stream));
+  }
+  a.step_ctr = nullptr;
+  for (int k = full * T; k < nsteps; ++k) {
+    a.step = k;
+    HIP_TRY(launch(a, stream));
+  }
+  return FWI_OK;
+}
+
+int upload_tables(const Plan& p, void* ws, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.shots), p.shots.data(), sizeof(ShotDesc) * p.shots.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.slots), p.slots.data(), sizeof(SlotInfo) * p.slots.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rdir), p.rdir.data(), sizeof(RmapDir) * p.rdir.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rrows), p.rrows.data(), sizeof(RmapRow) * p.rrows.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rmaps), p.rmaps.data(), sizeof(int32_t) * p.rmaps.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.trace_shot), p.trace_shot.data(),
+                         sizeof(int32_t) * p.trace_shot.size(), hipMemcpyHostToDevice, s));
+  return FWI_OK;
+}
+
+// prepares the workspace for a call: tables, cleared error flag, w = dt^2 v^2/h^2
+int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s) {
+  int rc = upload_tables(p, ws, s);
+  if (rc) return rc;
+  Header* hd = at<Header>(ws, p.L.hdr);
+  HIP_TRY(launch_set(&hd->err, 0, s));
+  const float vmax = (float)(FWI_CFL_LIMIT * p.dx / p.dt);
+  HIP_TRY(launch_prep(p.d, v, at<float>(ws, p.L.w), p.dt, p.dx, vmax, &hd->err, s));
+  return FWI_OK;
+}
+
+int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int64_t wstride,
+                  hipStream_t s) {
+  const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), 2 * p.d.field, 2 * p.d.field, slots, p.S, 1, s));
+  return run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
+}
+
+int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipStream_t s) {
+  MisfitArgs m{};
+  m.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
+  m.shots = at<ShotDesc>(ws, p.L.shots);
+  m.traces = at<float>(ws, p.L.traces);
+  m.dobs = d_obs;
+  m.ntrace = std::max(p.ntrace, 1);
+  m.nt_max = p.nt_max;
+  m.kind = misfit;
+  m.dt = p.dt;
+  m.psi_scale = (double)p.dx * p.dx / ((double)p.dt * p.dt);
+  m.Jpart = at<double>(ws, p.L.jpart);
+  m.err = &at<Header>(ws, p.L.hdr)->err;
+  HIP_TRY(launch_misfit(m, p.S, p.max_nrec, s));
+  return FWI_OK;
+}
+
+int reverse_batch(Plan& p, void* ws, int b, const float* wavelet, int64_t wstride, hipStream_t s) {
+  const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), 2 * p.d.field, 2 * p.d.field, slots, p.S, 0, s));
+  return run_steps(p, ws, b, kPhaseRev, 0, p.batch_nt[b] - 1, wavelet, wstride, s);
+}
+
+int epilogue_batch(Plan& p, void* ws, int b, const float* v, float* H1, float* D, int hmax,
+                   int rcv_model, hipStream_t s) {
+  if (!H1 && !D) return FWI_OK;
+  EpiArgs e{};
+  e.d = p.d;
+  e.S = p.S;
+  e.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
+  e.shots = at<ShotDesc>(ws, p.L.shots);
+  e.E = at<float>(ws, p.L.E);
+  e.v = v;
+  e.H1 = H1;
+  e.D = D;
+  e.hmax = D ? hmax : 0;
+  e.rcv_none = (rcv_model == FWI_RCV_NONE);
+  e.h = p.dx;
+  e.inv_dt3 = (float)(1.0 / ((double)p.dt * p.dt * p.dt));
+  e.err = &at<Header>(ws, p.L.hdr)->err;
+  HIP_TRY(launch_epilogue(e, s));
+  return FWI_OK;
+}
+
+int check_outputs_hess(int hmax, int rcv_model, float* D, const fwi_grid* g) {
+  if (D) {
+    if (hmax < 0 || hmax > 64) return fail(FWI_ERR_ARG, "hmax must be in [0, 64]");
+    if (hmax >= g->nx) return fail(FWI_ERR_ARG, "hmax must be < nx");
+    if (rcv_model != FWI_RCV_PM && rcv_model != FWI_RCV_NONE) return fail(FWI_ERR_ARG, "bad rcv_model");
+  }
+  return FWI_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+double time_steps(Plan& p, void* ws, int flags, int phase, int nsteps, const float* wavelet,
+                  int64_t wstride, hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 1e30;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return 1e30;
+  }
+  double ms = 1e30;
+  if (run_steps(p, ws, 0, phase, flags, 2, wavelet, wstride, s) == FWI_OK &&
+      hipEventRecord(e0, s) == hipSuccess &&
+      run_steps(p, ws, 0, phase, flags, nsteps, wavelet, wstride, s) == FWI_OK &&
+      hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+    float f = 0.0f;
+    if (hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = f;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return ms;
+}
+
+// Chooses rows per tile and shots in flight by timing a few steps of the
+// phases the call will run; results are cached per (grid, geometry, what).
+int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, uint64_t ikey,
+             void* ws, size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride,
+             hipStream_t s, ExecChoice& best) {
+  const int ns = geo->nshot;
+  const int Smax = best.S;
+  std::vector<int> Ss, TZs;
+  if (ex && ex->shots_in_flight > 0) Ss = {ex->shots_in_flight};
+  else
+    for (int c : {8, 16, 32, 64})
+      if (c <= Smax) Ss.push_back(c);
+  if (Ss.empty()) Ss = {Smax};
+  if (ex && ex->tile_rows > 0) TZs = {ex->tile_rows};
+  else TZs = {32, 64, 128};
+  double best_rate = -1.0;
+  ExecChoice choice = best;
+  for (int S : Ss) {
+    for (int TZ : TZs) {
+      ExecChoice c{S, TZ, best.graph_steps};
+      auto p = build_plan(g, geo, c, 0, what, 0);
+      if (p->L.total > ws_bytes) continue;
+      if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
+      HIP_TRY(launch_fill(at<char>(ws, p->L.u), p->L.g - p->L.u, s));
+      const int nsteps = 8;
+      const int shots = std::min(S, ns);
+      double ms = time_steps(*p, ws, kFwdRecord, kPhaseFwd, nsteps, wavelet, wstride, s);
+      if (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD)
+        ms += 2.75 * time_steps(*p, ws, 0, kPhaseRev, nsteps, wavelet, wstride, s);
+      const double rate = (double)shots / ms;
+      if (rate > best_rate) {
+        best_rate = rate;
+        choice = c;
+      }
+    }
+  }
+  (void)ikey;
+  best = choice;
+  return FWI_OK;
+}
+
+// ---------------------------------------------------------------- plan lookup
+struct CallCtx {
+  std::shared_ptr<Plan> plan;
+};
+
+ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex) {
+  ExecChoice c{};
+  const int Z = g->nz + 2 * g->nsponge;
+  c.S = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : default_shots_in_flight(geo->nshot);
+  c.TZ = (ex && ex->tile_rows > 0) ? ex->tile_rows : default_tile_rows(Z);
+  c.graph_steps = (ex && ex->graph_steps != 0) ? ex->graph_steps : 32;
+  return c;
+}
+
+std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what) {
+  Hasher h;
+  h.pod(*g);
+  h.pod(geo->nshot);
+  std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
+                             (uint64_t)(ex ? ex->tile_rows : 0)};
+  int ntmax = 0, nrmax = 0;
+  for (int s = 0; s < geo->nshot; ++s) {
+    ntmax = std::max(ntmax, shot_nt(g, geo, s));
+    nrmax = std::max(nrmax, geo->rec_ptr[s + 1] - geo->rec_ptr[s]);
+  }
+  k.push_back((uint64_t)ntmax);
+  k.push_back((uint64_t)nrmax);
+  int dev = 0;
+  hipGetDevice(&dev);
+  k.push_back((uint64_t)dev);
+  return k;
+}
+
+// Returns the plan for a call; with autotuning requested and no cached
+// choice, runs the tuner inside `ws` first (needs a workspace sized for the
+// untuned maximum, which fwi_workspace_bytes reports).
+int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, void* ws,
+             size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride, hipStream_t s,
+             std::shared_ptr<Plan>& out, bool sizing_only) {
+  const int plain = ex && ex->mode == FWI_EXEC_PLAIN;
+  if (ex && ex->mode != FWI_EXEC_PLAIN && ex->mode != FWI_EXEC_BATCHED) return fail(FWI_ERR_ARG, "bad exec mode");
+  if (ex && (ex->shots_in_flight < 0 || ex->tile_rows < 0 || ex->graph_steps < -1))
+    return fail(FWI_ERR_ARG, "bad exec settings");
+  if (ex && ex->tile_rows > 0 && ex->tile_rows < 8) return fail(FWI_ERR_ARG, "tile_rows must be >= 8");
+  ExecChoice c = base_choice(g, geo, ex);
+  const bool tune = !plain && ex && ex->autotune && !sizing_only;
+  const uint64_t ikey = inputs_hash(g, geo);
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (!plain && ex && ex->autotune) {
+    // the workspace is sized for the largest candidate
+    if (!(ex->shots_in_flight > 0)) c.S = std::min(std::max(geo->nshot, 1), 64);
+    if (!(ex->tile_rows > 0)) c.TZ = 32;
+  }
+  if (tune) {
+    const auto tk = tune_key(g, geo, ex, what);
+    auto it = g_tuned.find(tk);
+    if (it != g_tuned.end()) {
+      c = it->second;
+    } else {
+      ExecChoice t = c;
+      int rc = autotune(g, geo, ex, what, ikey, ws, ws_bytes, v, wavelet, wstride, s, t);
+      if (rc) return rc;
+      g_tuned[tk] = t;
+      c = t;
+    }
+  }
+  Hasher h;
+  h.pod(ikey);
+  h.pod(what == FWI_WS_AUTOGRAD ? FWI_WS_AUTOGRAD : what);
+  h.pod(plain);
+  h.pod(c.S);
+  h.pod(c.TZ);
+  h.pod(c.graph_steps);
+  const uint64_t key = h.h;
+  for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+    if ((*it)->key == key) {
+      out = *it;
+      g_plans.splice(g_plans.begin(), g_plans, it);
+      return FWI_OK;
+    }
+  }
+  out = build_plan(g, geo, c, plain, what, key);
+  out->ikey = ikey;
+  if (!sizing_only) {
+    g_plans.push_front(out);
+    while (g_plans.size() > 16) g_plans.pop_back();
+  }
+  return FWI_OK;
+}
+
+int common_checks(const fwi_grid* g, const fwi_geometry* geo, const float* v, const float* wavelet,
+                  int64_t wstride, void* ws) {
+  int rc = check_inputs(g, geo);
+  if (rc) return rc;
+  if (!v || !wavelet || !ws) return fail(FWI_ERR_ARG, "v, wavelet and workspace must not be NULL");
+  if (wstride != 0 && wstride < g->nt_max) return fail(FWI_ERR_ARG, "wavelet_stride must be 0 or >= nt_max");
+  return FWI_OK;
+}
+
+int ws_check(const Plan& p, size_t ws_bytes) {
+  if (ws_bytes < p.L.total)
+    return fail(FWI_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                       std::to_string(p.L.total));
+  return FWI_OK;
+}
+
+}  // namespace
+}  // namespace fwi
+
+using namespace fwi;
+
+// =====================================================================
+// C ABI
+// =====================================================================
+extern "C" {
+
+const char* fwi_last_error(void) { return g_last_error.c_str(); }
+
+int fwi_validate(const fwi_grid* grid, const fwi_geometry* geom) { return check_inputs(grid, geom); }
+
+size_t fwi_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, int what,
+                           int hmax) {
+  if (what == FWI_WS_PRECOND) return sizeof(Header);
+  if (check_inputs(grid, geom)) return 0;
+  if (what < FWI_WS_FORWARD || what > FWI_WS_AUTOGRAD) {
+    fail(FWI_ERR_ARG, "bad `what`");
+    return 0;
+  }
+  (void)hmax;
+  std::shared_ptr<Plan> p;
+  if (get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, nullptr, p, true)) return 0;
+  return p->L.total;
+}
+
+int fwi_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                const float* wavelet, int64_t wavelet_stride, float* data, void* workspace, size_t ws_bytes,
+                void* hip_stream) {
+  int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
+  if (rc) return rc;
+  if (!data && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "data must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::shared_ptr<Plan> p;
+  {
+    std::shared_ptr<Plan> sz;
+    if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = ws_check(*sz, ws_bytes))) return rc;
+  }
+  if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, workspace, ws_bytes, v, wavelet, wavelet_stride, s, p,
+                     false)))
+    return rc;
+  if ((rc = ws_check(*p, ws_bytes))) return rc;
+  if (geom->nshot == 0) return FWI_OK;
+  if ((rc = begin_call(*p, workspace, v, s))) return rc;
+  for (int b = 0; b < p->nbatch; ++b)
+    if ((rc = forward_batch(*p, workspace, b, kFwdRecord, wavelet, wavelet_stride, s))) return rc;
+  HIP_TRY(launch_traces_out(at<float>(workspace, p->L.traces), p->ntrace, p->nt_max,
+                            at<ShotDesc>(workspace, p->L.shots), at<int32_t>(workspace, p->L.trace_shot), data,
+                            s));
+  return FWI_OK;
+}
+
+static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                         const float* wavelet, int64_t wstride, const float* d_obs, int misfit, double* J,
+                         const double* grad_scale, float* grad, float* illum, int hmax, int rcv_model,
+                         float* offset_diag, void* ws, size_t ws_bytes, hipStream_t s, int part) {
+  // part: 0 = whole gradient, 1 = forward half (split), 2 = backward half (split)
+  int rc = common_checks(grid, geom, v, wavelet, wstride, ws);
+  if (rc) return rc;
+  if ((rc = check_outputs_hess(hmax, rcv_model, offset_diag, grid))) return rc;
+  const int what = part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD;
+  if (part != 2) {
+    if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL) return fail(FWI_ERR_ARG, "bad misfit");
+    if (!J) return fail(FWI_ERR_ARG, "J must not be NULL");
+    if (!d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "d_obs must not be NULL");
+  }
+  if (part != 1 && !grad) return fail(FWI_ERR_ARG, "grad must not be NULL");
+  std::shared_ptr<Plan> p;
+  {
+    std::shared_ptr<Plan> sz;
+    if ((rc = get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = ws_check(*sz, ws_bytes))) return rc;
+  }
+  if (part == 2) {
+    // the backward half must use the plan and workspace of the forward half
+    std::lock_guard<std::mutex> lock(g_mutex);
+    const uint64_t ikey = inputs_hash(grid, geom);
+    for (auto& cand : g_plans)
+      if (cand->split && cand->ikey == ikey && cand->fwd_ws == ws && cand->fwd_v == v &&
+          cand->fwd_wavelet == wavelet) {
+        p = cand;
+        break;
+      }
+    if (!p) return fail(FWI_ERR_STATE, "fwi_misfit_backward without a matching fwi_misfit_forward");
+  } else {
+    if ((rc = get_plan(grid, geom, exec, what, ws, ws_bytes, v, wavelet, wstride, s, p, false))) return rc;
+  }
+  if ((rc = ws_check(*p, ws_bytes))) return rc;
+  const Plan& cp = *p;
+  const size_t model_bytes = sizeof(float) * cp.d.model;
+  Header* hd = at<Header>(ws, cp.L.hdr);
+
+  if (part != 2) {
+    if ((rc = begin_call(*p, ws, v, s))) return rc;
+    if (part == 1) {
+      p->fwd_ws = nullptr;
+    }
+  }
+  if (part != 1) {
+    HIP_TRY(launch_fill(at<float>(ws, cp.L.g), model_bytes * cp.S, s));
+    if (illum) HIP_TRY(launch_fill(illum, model_bytes, s));
+    if (offset_diag) HIP_TRY(launch_fill(offset_diag, model_bytes * (2 * hmax + 1), s));
+  }
+  for (int b = 0; b < cp.nbatch; ++b) {
+    if (part != 2) {
+      if ((rc = forward_batch(*p, ws, b, kFwdRecord | kFwdCkpt, wavelet, wstride, s))) return rc;
+      if ((rc = misfit_batch(*p, ws, b, d_obs, misfit, s))) return rc;
+    }
+    if (part == 0) {
+      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s))) return rc;
+      if ((rc = epilogue_batch(*p, ws, b, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
+    }
+  }
+  if (part == 2) {
+    for (int b = 0; b < cp.nbatch; ++b) {
+      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s))) return rc;
+      if ((rc = epilogue_batch(*p, ws, b, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
+    }
+  }
+  if (part != 2) {
+    if (cp.ntrace > 0) {
+      HIP_TRY(launch_reduce_J(at<double>(ws, cp.L.jpart), cp.ntrace, J, &hd->err, s));
+    } else {
+      HIP_TRY(launch_fill(J, sizeof(double), s));
+    }
+  }
+  if (part != 1) {
+    HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.S, v, grad_scale, grad, &hd->err, s));
+  }
+  if (part == 1) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    p->fwd_ws = ws;
+    p->fwd_v = v;
+    p->fwd_wavelet = wavelet;
+  }
+  return FWI_OK;
+}
+
+int fwi_gradient(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                 const float* wavelet, int64_t wavelet_stride, const float* d_obs, int misfit, double* J,
+                 float* grad, float* illum, int hmax, int rcv_model, float* offset_diag, void* workspace,
+                 size_t ws_bytes, void* hip_stream) {
+  return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, illum,
+                       hmax, rcv_model, offset_diag, workspace, ws_bytes, (hipStream_t)hip_stream, 0);
+}
+
+int fwi_misfit_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                       const float* wavelet, int64_t wavelet_stride, const float* d_obs, int misfit, double* J,
+                       void* workspace, size_t ws_bytes, void* hip_stream) {
+  return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, nullptr,
+                       nullptr, 0, FWI_RCV_PM, nullptr, workspace, ws_bytes, (hipStream_t)hip_stream, 1);
+}
+
+int fwi_misfit_backward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                        const float* wavelet, int64_t wavelet_stride, const double* grad_scale, float* grad,
+                        float* illum, int hmax, int rcv_model, float* offset_diag, void* workspace,
+                        size_t ws_bytes, void* hip_stream) {
+  return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, nullptr, FWI_MISFIT_L2, nullptr, grad_scale,
+                       grad, illum, hmax, rcv_model, offset_diag, workspace, ws_bytes, (hipStream_t)hip_stream,
+                       2);
+}
+
+int fwi_hessian_diag(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                     const float* wavelet, int64_t wavelet_stride, int kind, int hmax, int rcv_model, float* diag,
+                     void* workspace, size_t ws_bytes, void* hip_stream) {
+  int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
+  if (rc) return rc;
+  if (kind != FWI_HESS_EQ1 && kind != FWI_HESS_OFFSET) return fail(FWI_ERR_ARG, "bad kind");
+  if (!diag) return fail(FWI_ERR_ARG, "diag must not be NULL");
+  float* H1 = kind == FWI_HESS_EQ1 ? diag : nullptr;
+  float* D = kind == FWI_HESS_OFFSET ? diag : nullptr;
+  if ((rc = check_outputs_hess(hmax, rcv_model, D, grid))) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::shared_ptr<Plan> p;
+  {
+    std::shared_ptr<Plan> sz;
+    if ((rc = get_plan(grid, geom, exec, FWI_WS_HESSIAN, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = ws_check(*sz, ws_bytes))) return rc;
+  }
+  if ((rc = get_plan(grid, geom, exec, FWI_WS_HESSIAN, workspace, ws_bytes, v, wavelet, wavelet_stride, s, p,
+                     false)))
+    return rc;
+  if ((rc = ws_check(*p, ws_bytes))) return rc;
+  const size_t model_bytes = sizeof(float) * p->d.model;
+  HIP_TRY(launch_fill(diag, model_bytes * (D ? (2 * hmax + 1) : 1), s));
+  if (geom->nshot == 0) return FWI_OK;
+  if ((rc = begin_call(*p, workspace, v, s))) return rc;
+  for (int b = 0; b < p->nbatch; ++b) {
+    if ((rc = forward_batch(*p, workspace, b, kFwdIllum, wavelet, wavelet_stride, s))) return rc;
+    if ((rc = epilogue_batch(*p, workspace, b, v, H1, D, hmax, rcv_model, s))) return rc;
+  }
+  return FWI_OK;
+}
+
+int fwi_precondition(const fwi_grid* grid, const float* v, const float* grad, int kind, const float* hdiag,
+                     int hmax, float eps, float* out, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!grid || !v || !grad || !hdiag || !out || !workspace) return fail(FWI_ERR_ARG, "NULL argument");
+  if (grid->nz < 1 || grid->nx < 1) return fail(FWI_ERR_ARG, "nz and nx must be >= 1");
+  if (kind != FWI_PRECOND_SHOT && kind != FWI_PRECOND_OFFSET) return fail(FWI_ERR_ARG, "bad kind");
+  if (kind == FWI_PRECOND_OFFSET && (hmax < 0 || hmax > 64)) return fail(FWI_ERR_ARG, "hmax must be in [0, 64]");
+  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(FWI_ERR_ARG, "eps must be >= 0");
+  if (ws_bytes < sizeof(Header)) return fail(FWI_ERR_WORKSPACE, "precondition workspace too small");
+  Header* hd = (Header*)workspace;
+  HIP_TRY(launch_precond(grid->nz, grid->nx, v, grad, kind, hdiag, kind == FWI_PRECOND_OFFSET ? hmax : 0, eps,
+                         out, &hd->maxbits, (hipStream_t)hip_stream));
+  return FWI_OK;
+}
+
+int fwi_status(const void* workspace, void* hip_stream) {
+  if (!workspace) return fail(FWI_ERR_ARG, "workspace must not be NULL");
+  int32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, workspace, sizeof(int32_t), hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+  if (err) return fail(FWI_ERR_NONFINITE, "velocity non-finite, non-positive or above the CFL bound");
+  return FWI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute call).
+
+The library must load, export every function include/fwi.h declares, and
+reject bad input with the documented error code before it touches the GPU
+(every check below returns before any HIP call is made).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1406_1864_amd import binding as B
+from paper_1406_1864_amd.synthetic import Grid, Geometry, tiny_24x16, layered_1024x384, ragged_1024x384
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = B.header_functions()
+    assert len(names) >= 10, names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _tiny():
+    w = tiny_24x16(nt=64)
+    return w.grid, w.geom
+
+
+def test_validate_ok(lib):
+    g, geo = _tiny()
+    assert B.fwi_validate(g, geo) == B.FWI_OK
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda g, geo: setattr(g, "v_ref", 6000.0), B.FWI_ERR_CFL),
+    (lambda g, geo: setattr(g, "nsponge", 3), B.FWI_ERR_ARG),
+    (lambda g, geo: setattr(g, "dt", 0.0), B.FWI_ERR_ARG),
+    (lambda g, geo: setattr(g, "nt_max", 1), B.FWI_ERR_ARG),
+    (lambda g, geo: geo.src_ix.__setitem__(0, 24), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.src_iz.__setitem__(1, -1), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.rec_ix.__setitem__(3, 99), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.rec_ix.__setitem__(1, geo.rec_ix[0]), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.nt.__setitem__(0, 65), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.nt.__setitem__(0, 1), B.FWI_ERR_GEOM),
+    (lambda g, geo: geo.rec_ptr.__setitem__(1, 7), B.FWI_ERR_GEOM),
+])
+def test_validate_rejects(lib, mutate, code):
+    g, geo = _tiny()
+    mutate(g, geo)
+    assert B.fwi_validate(g, geo) == code
+    assert len(B.last_error()) > 0
+
+
+def test_cfl_bound_matches_scheme():
+    import oracle
+    assert abs(B.FWI_CFL_LIMIT - oracle.CFL_LIMIT) < 1e-15
+    g, geo = _tiny()
+    g.v_ref = 0.999 * B.FWI_CFL_LIMIT * g.dx / g.dt
+    assert B.fwi_validate(g, geo) == B.FWI_OK
+    g.v_ref = 1.001 * B.FWI_CFL_LIMIT * g.dx / g.dt
+    assert B.fwi_validate(g, geo) == B.FWI_ERR_CFL
+
+
+def test_workspace_sizes(lib):
+    g, geo = _tiny()
+    fwd = B.fwi_workspace_bytes(g, geo, None, B.WS_FORWARD)
+    grad = B.fwi_workspace_bytes(g, geo, None, B.WS_GRADIENT)
+    auto = B.fwi_workspace_bytes(g, geo, None, B.WS_AUTOGRAD)
+    hess = B.fwi_workspace_bytes(g, geo, None, B.WS_HESSIAN)
+    assert 0 < fwd < hess < grad <= auto
+    assert B.fwi_workspace_bytes(g, geo, None, B.WS_PRECOND) >= 4
+    g.v_ref = 1e5
+    assert B.fwi_workspace_bytes(g, geo, None, B.WS_GRADIENT) == 0
+
+
+def test_workspace_fits_an_mi355x_at_full_sizes(lib):
+    """The checkpoints of the batched gradient fit in 288 GB of HBM."""
+    for w in (layered_1024x384(), ragged_1024x384()):
+        ex = B.make_exec(shots_in_flight=64)
+        n = B.fwi_workspace_bytes(w.grid, w.geom, ex, B.WS_GRADIENT)
+        assert 0 < n < 200e9, (w.name, n)
+
+
+def test_entry_points_reject_before_launch(lib):
+    """Bad arguments come back as error codes with no HIP call (fake device
+    pointers are never dereferenced)."""
+    g, geo = _tiny()
+    fake = 0x1000
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_forward(g, geo, None, fake, fake, 0, fake, fake, 16, stream=0)
+    assert e.value.code == B.FWI_ERR_WORKSPACE
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_gradient(g, geo, None, fake, fake, 0, fake, "int", fake, fake, None, 0, "pm", None, fake, 16,
+                       stream=0)
+    assert e.value.code == B.FWI_ERR_WORKSPACE
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_gradient(g, geo, None, fake, fake, 0, fake, "int", fake, fake, None, 99, "pm", fake, fake, 1 << 40,
+                       stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_forward(g, geo, None, fake, fake, 7, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    g.v_ref = 1e5
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_hessian_diag(g, geo, None, fake, fake, 0, B.HESS_EQ1, 0, "pm", fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_CFL
+    g, geo = _tiny()
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_misfit_backward(g, geo, None, fake, fake, 0, None, fake, None, 0, "pm", None, fake, 1 << 40,
+                              stream=0)
+    assert e.value.code == B.FWI_ERR_STATE
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_precondition(g, fake, fake, 5, fake, 0, 0.01, fake, fake, 256, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG

@@ -1,0 +1,85 @@
+"""GPU parity at full grid sizes against stored FP64 oracle values.
+
+The oracle values come from tests/golden/make_golden.py (oracle only) and
+hold a regular subsample of the outputs; the GPU runs the same inputs,
+regenerated here from the same seeds, in the batched launch configurations
+the benchmark uses, and the subsample is compared with the same relative-L2
+tolerances as the small cases.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1406_1864_amd import binding as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_golden  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TRACE_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", name + ".npz")
+    z = np.load(path)
+    w, grid, geom, wav, seed = make_golden.case_inputs(name)
+    from paper_1406_1864_amd.synthetic import random_traces
+    d_obs = random_traces(geom, grid.nt_max, seed=seed, scale=float(z["scale"]))
+    return z, w, grid, geom, wav, d_obs
+
+
+def check(z, J, g, H1, traces, mult=1.0, D=None):
+    zs, rs, ts = int(z["zs"]), int(z["rs"]), int(z["ts"])
+    assert abs(J - mult * float(z["J"])) <= TRACE_TOL * mult * float(z["J"])
+    assert rel(g[::zs, ::zs], mult * z["g"]) < GRAD_TOL
+    assert rel(H1[::zs, ::zs], mult * z["H1"]) < GRAD_TOL
+    ntr = z["traces"].shape[0]
+    assert rel(traces[::rs, ::ts][:ntr], z["traces"]) < TRACE_TOL
+    if D is not None:
+        assert rel(D[::4, ::zs, ::zs], mult * z["D"]) < GRAD_TOL
+
+
+@pytest.mark.parametrize("S,TZ", [(8, 64), (8, 32), (8, 128), (4, 64)])
+def test_layered_1024x384_short_record(S, TZ):
+    """8 shots = the 2 stored shots repeated 4 times, so that the batched
+    launch fills 8 slots (one per XCD) and the result is 4x the oracle's."""
+    name = "layered_1024x384_nt400"
+    z, w, grid, geom2, wav, d2 = golden(name)
+    geom = geom2.subset([0, 1] * 4)
+    d_obs = np.concatenate([d2] * 4)
+    ex = B.make_exec(shots_in_flight=S, tile_rows=TZ)
+    tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
+    J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
+    rs = int(z["rs"])
+    nrec = geom2.rec_ptr[1]
+    both = np.concatenate([tr[0:nrec:rs], tr[nrec:2 * nrec:rs]])
+    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), np.repeat(both, rs, axis=0), mult=4.0)
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_layered_1024x384_full_record(mode):
+    z, w, grid, geom, wav, d_obs = golden("layered_1024x384_nt4000")
+    ex = B.make_exec(mode=B.EXEC_PLAIN) if mode == "plain" else B.make_exec(autotune=1)
+    tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
+    J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
+    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr)
+
+
+def test_layered_2048x768_full_record_offset_diag():
+    z, w, grid, geom, wav, d_obs = golden("layered_2048x768_nt8000")
+    ex = B.make_exec(autotune=1)
+    tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
+    J, g, H1, D = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex, hmax=int(z["hmax"]))
+    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr, D=D.cpu().numpy())
