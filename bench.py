@@ -190,6 +190,7 @@ def main():
     fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
                           for s in range(shots)))
     traffic = measured_traffic("k_reverse", None)
+    chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
     out = {
         "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
         "value": value,
@@ -205,7 +206,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name if shots == 64 else f"{w.name} ({shots} shots)", "shots": shots,
                    "grid": [grid.nz, grid.nx], "padded": [Z, X], "nt": int(nt.max()), "receivers_per_shot": 512,
-                   "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned"},
+                   "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned",
+                   "shots_in_flight": chosen["shots_in_flight"], "tile_rows": chosen["tile_rows"],
+                   "graph_steps": chosen["graph_steps"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},

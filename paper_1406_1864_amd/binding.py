@@ -65,13 +65,15 @@ class fwi_geometry(ctypes.Structure):
 
 class fwi_exec(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("shots_in_flight", c_int32), ("tile_rows", c_int32),
-                ("graph_steps", c_int32), ("autotune", c_int32)]
+                ("graph_steps", c_int32), ("autotune", c_int32), ("prefetch", c_int32)]
 
 
 _lib = None
 _SIGS = {
     "fwi_workspace_bytes": (c_size_t, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_int, c_int]),
     "fwi_validate": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry)]),
+    "fwi_exec_query": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_int,
+                               POINTER(fwi_exec)]),
     "fwi_forward": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
                             c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_gradient": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
@@ -147,8 +149,10 @@ class GeometryC:
         self.struct = fwi_geometry(int(geom.nshot), *ptrs)
 
 
-def make_exec(mode=EXEC_BATCHED, shots_in_flight=0, tile_rows=0, graph_steps=0, autotune=0) -> fwi_exec:
-    return fwi_exec(int(mode), int(shots_in_flight), int(tile_rows), int(graph_steps), int(autotune))
+def make_exec(mode=EXEC_BATCHED, shots_in_flight=0, tile_rows=0, graph_steps=0, autotune=0,
+              prefetch=0) -> fwi_exec:
+    return fwi_exec(int(mode), int(shots_in_flight), int(tile_rows), int(graph_steps), int(autotune),
+                    int(prefetch))
 
 
 def _ptr(t):
@@ -184,6 +188,13 @@ def fwi_workspace_bytes(grid, geom, exec_, what, hmax=0) -> int:
 def fwi_validate(grid, geom) -> int:
     g, G = make_grid(grid), _geo(geom)
     return int(load().fwi_validate(ctypes.byref(g), ctypes.byref(G.struct)))
+
+
+def fwi_exec_query(grid, geom, exec_, what) -> dict:
+    g, G = make_grid(grid), _geo(geom)
+    out = fwi_exec()
+    _check(load().fwi_exec_query(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), int(what), ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in fwi_exec._fields_}
 
 
 def fwi_forward(grid, geom, exec_, v, wavelet, wavelet_stride, data, workspace, ws_bytes, stream=None):

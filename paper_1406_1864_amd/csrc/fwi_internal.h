@@ -112,8 +112,9 @@ hipError_t launch_prep(const Dims& d, const float* v, float* w, float dt, float 
 hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s);
 hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,
                              int S, int use_cs, hipStream_t s);
-hipError_t launch_forward(const StepArgs& a, int flags, hipStream_t s);
-hipError_t launch_reverse(const StepArgs& a, hipStream_t s);
+// prefetch: rows of loads in flight ahead of the sweep (forward 1, 3, 7; reverse 1, 3)
+hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s);
+hipError_t launch_reverse(const StepArgs& a, int prefetch, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);
 hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s);
 hipError_t launch_misfit(const MisfitArgs& a, int S, int max_nrec, hipStream_t s);

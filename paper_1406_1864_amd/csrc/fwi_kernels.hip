@@ -77,23 +77,96 @@ __device__ __forceinline__ int step_of(const StepArgs& a) {
   return a.step_ctr ? (*a.step_ctr + a.step) : a.step;
 }
 
-// boundary-strip index of padded cell (z, x) or -1 (ring: the 4 cells just
-// outside the model on each side, corners excluded)
-__device__ __forceinline__ int ring_index(const Dims& d, int z, int x) {
-  const int mz = z - d.N, mx = x - d.N;
-  const bool zin = mz >= 0 && mz < d.nz, xin = mx >= 0 && mx < d.nx;
-  if (xin && mz >= -kRadius && mz < 0) return (mz + kRadius) * d.nx + mx;
-  if (xin && mz >= d.nz && mz < d.nz + kRadius) return 4 * d.nx + (mz - d.nz) * d.nx + mx;
-  if (zin && mx >= -kRadius && mx < 0) return 8 * d.nx + mz * 4 + (mx + kRadius);
-  if (zin && mx >= d.nx && mx < d.nx + kRadius) return 8 * d.nx + 4 * d.nz + mz * 4 + (mx - d.nx);
-  return -1;
+// Per-lane column classification of a wavefront tile (computed once).
+struct Col {
+  int xs;      // storage column
+  int x;       // padded column
+  bool xin;    // inside the padded grid
+  int dxs;     // cells into the sponge along x (0 inside the model columns)
+  int mx;      // model column (valid if mcol)
+  bool mcol;   // model column
+  int side;    // strip index base of a left/right ring column, -1 otherwise
+  int hcol;    // halo column held by lanes 0..7
+  bool hok;    // this lane loads a halo value
+};
+
+__device__ __forceinline__ Col make_col(const Dims& d, int xs0, int lane) {
+  Col c;
+  c.xs = xs0 + lane;
+  c.x = c.xs - d.off;
+  c.xin = c.x >= 0 && c.x < d.X;
+  c.dxs = max(max(d.N - c.x, c.x - (d.N + d.nx - 1)), 0);
+  c.mx = c.xs - d.mx0;
+  c.mcol = c.mx >= 0 && c.mx < d.nx;
+  c.side = (c.mx >= -kRadius && c.mx < 0) ? 8 * d.nx + (c.mx + kRadius)
+           : (c.mx >= d.nx && c.mx < d.nx + kRadius) ? 8 * d.nx + 4 * d.nz + (c.mx - d.nx) : -1;
+  c.hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
+  c.hok = lane < 8 && c.hcol >= 0 && c.hcol < d.P;
+  return c;
+}
+
+// Uniform classification of one padded row.
+struct Row {
+  int mz;      // model row
+  bool model;  // model row
+  int dz;      // cells into the sponge along z
+  int tb;      // strip index base of a top/bottom ring row, -1 otherwise
+};
+
+__device__ __forceinline__ Row make_row(const Dims& d, int z) {
+  Row r;
+  r.mz = z - d.N;
+  r.model = r.mz >= 0 && r.mz < d.nz;
+  r.dz = max(max(-r.mz, r.mz - (d.nz - 1)), 0);
+  r.tb = (r.mz >= -kRadius && r.mz < 0) ? (r.mz + kRadius) * d.nx
+         : (r.mz >= d.nz && r.mz < d.nz + kRadius) ? 4 * d.nx + (r.mz - d.nz) * d.nx : -1;
+  return r;
+}
+
+// strip index of cell (row, col) of the 4-cell ring around the model, or -1
+__device__ __forceinline__ int strip_index(const Row& r, const Col& c) {
+  if (r.model) return c.side >= 0 ? c.side + 4 * r.mz : -1;
+  return (r.tb >= 0 && c.mcol) ? r.tb + c.mx : -1;
+}
+
+// 8th-order Laplacian (times h^2) in difference form from the register
+// window (z neighbours) and the wavefront's LDS row (x neighbours).
+template <int W>
+__device__ __forceinline__ float laplace(const float (&win)[W], int ctr, const float* lds, int lane) {
+  const float c = win[ctr % W];
+  float lap = 0.0f;
+#pragma unroll
+  for (int k = 4; k >= 1; --k) {
+    const float sz = win[(ctr - k + W) % W] + win[(ctr + k) % W];
+    const float sx = lds[kRadius + lane - k] + lds[kRadius + lane + k];
+    lap = fmaf(ck(k), fmaf(-4.0f, c, sz + sx), lap);
+  }
+  return lap;
+}
+
+__device__ __forceinline__ void lds_put(float* lds, int lane, float c, float h) {
+  lds[kRadius + lane] = c;
+  if (lane < 4) lds[lane] = h;
+  else if (lane < 8) lds[kWave + lane] = h;
+}
+
+// FP64 damped update of a sponge cell: ((2c - (1-g) p + w lap) / (1+g))
+__device__ __forceinline__ float sponge_update(double sp_a, int dd, float c, float p, float w, float lap) {
+  const double gm = sp_a * (double)(dd * dd);
+  return (float)((2.0 * (double)c - (1.0 - gm) * (double)p + (double)w * (double)lap) / (1.0 + gm));
 }
 
 // -------------------------------------------------------------------------
-// forward step: u[n+1] from u[n], u[n-1] for every shot of the batch
+// forward step: u[n+1] from u[n], u[n-1] for every shot of the batch.
+// The z sweep keeps W = 9 + PF rows of u[n] in registers and issues the loads
+// of row z+4+PF (and the point-wise operands of row z+PF) PF rows ahead, so
+// several rows of loads are in flight per wavefront.
 // -------------------------------------------------------------------------
-template <int FLAGS>
+template <int FLAGS, int PF>
 __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
+  constexpr int W = 9 + PF;  // stencil-row ring
+  constexpr int R = PF + 1;  // point-wise ring; W % R == 0 keeps slots static
+  static_assert(W % R == 0, "prefetch distance must make the rings commensurate");
   __shared__ float lds_all[kWavesPerBlock][kWave + 2 * kRadius];
   const int lane = threadIdx.x & 63;
   const int wv = uniform(threadIdx.x >> 6);
@@ -109,18 +182,13 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   const Dims& d = a.d;
   float* lds = lds_all[wv];
   const int xt = tile % d.XT, zt = tile / d.XT;
-  const int xs0 = xt * kWave, xs = xs0 + lane, x = xs - d.off;
-  const bool xin = x >= 0 && x < d.X;
+  const int xs0 = xt * kWave;
+  const Col col = make_col(d, xs0, lane);
   const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
   float* ubase = a.u + (int64_t)si.cs * 2 * d.field;
   const float* ucur = ubase + (int64_t)(n & 1) * d.field;
   float* unxt = ubase + (int64_t)((n + 1) & 1) * d.field;
-  const int hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
-  const bool hok = lane < 8 && hcol >= 0 && hcol < d.P;
-  const int dxs = max(max(d.N - x, x - (d.N + d.nx - 1)), 0);
-  const int mx = xs - d.mx0;
 
-  // source cell of this shot inside the tile?
   const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
   const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + n] : 0.0f;
 
@@ -139,75 +207,68 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
     const int rem = sd.nt - 2 - n;  // nt-1 - (n+1)
     save = rem > 0 && (rem % sd.K) == 0;
     if (save) {
-      const int k = rem / sd.K;
-      snap0 = a.snap + (int64_t)si.cs * a.snap_stride + (int64_t)(k - 1) * 2 * d.model;
+      snap0 = a.snap + (int64_t)si.cs * a.snap_stride + (int64_t)(rem / sd.K - 1) * 2 * d.model;
       snap1 = snap0 + d.model;
     }
     strip = a.strip + (int64_t)si.cs * a.strip_stride + (int64_t)(n + 1) * d.ring;
   }
   float* E = (FLAGS & kFwdIllum) ? a.E + (int64_t)slot * d.model : nullptr;
 
-  float wc[9], wh[9];
+  float wc[W], wh[W], pu[R], pw[R];
   auto load_row = [&](int r, float& c, float& h) {
     if (r >= 0 && r < d.Z) {
       const float* row = ucur + (int64_t)r * d.P;
-      c = row[xs];
-      h = hok ? row[hcol] : 0.0f;
+      c = row[col.xs];
+      h = col.hok ? row[col.hcol] : 0.0f;
     } else {
       c = 0.0f;
       h = 0.0f;
     }
   };
+  auto load_pt = [&](int r, float& p, float& w) {
+    const int64_t idx = (int64_t)r * d.P + col.xs;
+    p = unxt[idx];
+    w = a.w[idx];
+  };
 #pragma unroll
-  for (int j = 0; j < 8; ++j) load_row(z0 - 4 + j, wc[j], wh[j]);
+  for (int j = 0; j < 8 + PF; ++j) load_row(z0 - 4 + j, wc[j], wh[j]);
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    if (z0 + j < z1) load_pt(z0 + j, pu[j], pw[j]);
 
-  for (int zb = z0; zb < z1; zb += 9) {
+  for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < W; ++r) {
       const int z = zb + r;
       if (z >= z1) break;
-      load_row(z + 4, wc[(r + 8) % 9], wh[(r + 8) % 9]);
-      const float c = wc[(r + 4) % 9];
-      lds[kRadius + lane] = c;
-      if (lane < 4) lds[lane] = wh[(r + 4) % 9];
-      else if (lane < 8) lds[kWave + lane] = wh[(r + 4) % 9];
-      wave_lds_fence();
-      float lap = 0.0f;
-#pragma unroll
-      for (int k = 4; k >= 1; --k) {
-        const float sz = wc[(r + 4 - k) % 9] + wc[(r + 4 + k) % 9];
-        const float sx = lds[kRadius + lane - k] + lds[kRadius + lane + k];
-        lap = fmaf(ck(k), fmaf(-4.0f, c, sz + sx), lap);
+      if (z + PF < z1) {
+        load_row(z + 4 + PF, wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
+        load_pt(z + PF, pu[(r + PF) % R], pw[(r + PF) % R]);
       }
+      const float c = wc[(r + 4) % W];
+      lds_put(lds, lane, c, wh[(r + 4) % W]);
       wave_lds_fence();
-      if (src_tile && z == sd.src_z && xs == sd.src_xs) lap += fsrc;
+      float lap = laplace<W>(wc, r + 4, lds, lane);
+      wave_lds_fence();
+      if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lap += fsrc;
 
-      const int64_t idx = (int64_t)z * d.P + xs;
+      const Row row = make_row(d, z);
+      const float up = pu[r % R], wv_ = pw[r % R];
       float out = 0.0f;
-      int dd = 0;
-      if (xin) {
-        const float up = unxt[idx];
-        const float wv_ = a.w[idx];
-        const int dz = max(max(d.N - z, z - (d.N + d.nz - 1)), 0);
-        dd = max(dz, dxs);
-        if (dd == 0) {
-          out = fmaf(wv_, lap, 2.0f * c - up);
-          if (FLAGS & kFwdIllum) {
-            const float D = wv_ * lap;
-            const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
-            E[mi] = (n == 0) ? D * D : fmaf(D, D, E[mi]);
-          }
-        } else {
-          const double gm = a.sp_a * (double)(dd * dd);
-          out = (float)((2.0 * (double)c - (1.0 - gm) * (double)up + (double)wv_ * (double)lap) /
-                        (1.0 + gm));
+      if (col.xin) {
+        const int dd = max(row.dz, col.dxs);
+        out = dd == 0 ? fmaf(wv_, lap, 2.0f * c - up) : sponge_update(a.sp_a, dd, c, up, wv_, lap);
+        unxt[(int64_t)z * d.P + col.xs] = out;
+        const bool mcell = row.model && col.mcol;
+        const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
+        if ((FLAGS & kFwdIllum) && mcell) {
+          const float D = wv_ * lap;
+          E[mi] = (n == 0) ? D * D : fmaf(D, D, E[mi]);
         }
-        unxt[idx] = out;
         if (FLAGS & kFwdCkpt) {
-          const int ri = ring_index(d, z, x);
+          const int ri = strip_index(row, col);
           if (ri >= 0) strip[ri] = out;
-          if (save && dd == 0) {
-            const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
+          if (save && mcell) {
             snap0[mi] = out;
             snap1[mi] = c;
           }
@@ -231,8 +292,13 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
 //   strip ring of u[m-2] restored from the forward's boundary strips
 //   lam[m] = damped leapfrog of lam[m+1], lam[m+2] + w psi'[m] at receivers
 //   g += lam[m] D[m],  E += D[m]^2,  D[m] = w (L u[m-1] + f[m-1] e_src)
+// Same register sweep and prefetch as the forward, for two fields.
 // -------------------------------------------------------------------------
+template <int PF>
 __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
+  constexpr int W = 9 + PF;
+  constexpr int R = PF + 1;
+  static_assert(W % R == 0, "prefetch distance must make the rings commensurate");
   __shared__ float ldsU_all[kWavesPerBlock][kWave + 2 * kRadius];
   __shared__ float ldsL_all[kWavesPerBlock][kWave + 2 * kRadius];
   const int lane = threadIdx.x & 63;
@@ -250,22 +316,17 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   float* ldsU = ldsU_all[wv];
   float* ldsL = ldsL_all[wv];
   const int xt = tile % d.XT, zt = tile / d.XT;
-  const int xs0 = xt * kWave, xs = xs0 + lane, x = xs - d.off;
-  const bool xin = x >= 0 && x < d.X;
+  const int xs0 = xt * kWave;
+  const Col col = make_col(d, xs0, lane);
+  const int hmx = col.hcol - d.mx0;
+  const bool hmcol = hmx >= 0 && hmx < d.nx;
   const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
   float* ubase = a.u + (int64_t)si.cs * 2 * d.field;
-  float* u_m = ubase + (int64_t)(m & 1) * d.field;          // u[m] in, u[m-2] out
+  float* u_m = ubase + (int64_t)(m & 1) * d.field;  // u[m] in, u[m-2] out
   const float* u_m1 = ubase + (int64_t)((m - 1) & 1) * d.field;
   float* lbase = a.lam + (int64_t)slot * 2 * d.field;
   const float* l_p1 = lbase + (int64_t)((m + 1) & 1) * d.field;  // lam[m+1]
   float* l_p2 = lbase + (int64_t)(m & 1) * d.field;              // lam[m+2] in, lam[m] out
-  const int hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
-  const bool hok = lane < 8 && hcol >= 0 && hcol < d.P;
-  const int dxs = max(max(d.N - x, x - (d.N + d.nx - 1)), 0);
-  const int mx = xs - d.mx0;
-  const int hmx = hcol - d.mx0;
-  const bool mcol = mx >= 0 && mx < d.nx;
-  const bool hmcol = hmx >= 0 && hmx < d.nx;
 
   // snapshot reset: at m == a_k the model cells of u[m] and u[m-1] come from
   // snapshot k, and at m == a_k - 1 u[m] comes from it again, so that both
@@ -278,6 +339,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const float* snap0 = reset ? ckpt + (int64_t)(rem / sd.K - 1) * 2 * d.model : nullptr;
   const float* snap1 = reset ? snap0 + d.model : nullptr;
   const float* snapp = reset_prev ? ckpt + (int64_t)((rem - 1) / sd.K - 1) * 2 * d.model + d.model : nullptr;
+  const float* u0src = reset ? snap0 : snapp;  // model-cell source of u[m] (null: u_m)
   const float* strip = (m >= 3) ? a.strip + (int64_t)si.cs * a.strip_stride + (int64_t)(m - 2) * d.ring
                                 : nullptr;
   const bool first = (m == sd.nt - 1);
@@ -298,17 +360,18 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const float* psi = a.traces + (int64_t)m * a.ntrace;
 
   const int uz_lo = d.N - kRadius, uz_hi = d.N + d.nz + kRadius;  // rows where u is defined
-  float uc[9], uh[9], lc[9], lh[9];
+  float uc[W], uh[W], lc[W], lh[W];
+  float p0[R], pl[R], pw[R], pg[R], pe[R];
   auto load_rows = [&](int r, float& cu, float& hu, float& cl, float& hl) {
     if (r >= 0 && r < d.Z) {
       const int64_t ro = (int64_t)r * d.P;
-      cl = l_p1[ro + xs];
-      hl = hok ? l_p1[ro + hcol] : 0.0f;
+      cl = l_p1[ro + col.xs];
+      hl = col.hok ? l_p1[ro + col.hcol] : 0.0f;
       if (r >= uz_lo && r < uz_hi) {
         const bool mrow = reset && r >= d.N && r < d.N + d.nz;
         const int64_t mo = (int64_t)(r - d.N) * d.nx;
-        cu = (mrow && mcol) ? snap1[mo + mx] : u_m1[ro + xs];
-        hu = hok ? ((mrow && hmcol) ? snap1[mo + hmx] : u_m1[ro + hcol]) : 0.0f;
+        cu = (mrow && col.mcol) ? snap1[mo + col.mx] : u_m1[ro + col.xs];
+        hu = col.hok ? ((mrow && hmcol) ? snap1[mo + hmx] : u_m1[ro + col.hcol]) : 0.0f;
       } else {
         cu = 0.0f;
         hu = 0.0f;
@@ -317,44 +380,44 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
       cu = hu = cl = hl = 0.0f;
     }
   };
+  auto load_pt = [&](int r, float& u0, float& l2, float& w, float& g, float& e) {
+    const int64_t idx = (int64_t)r * d.P + col.xs;
+    l2 = l_p2[idx];
+    w = a.w[idx];
+    const int mz = r - d.N;
+    if (mz >= 0 && mz < d.nz && col.mcol) {
+      const int64_t mi = (int64_t)mz * d.nx + col.mx;
+      u0 = u0src ? u0src[mi] : u_m[idx];
+      g = G[mi];
+      e = first ? 0.0f : E[mi];
+    } else {
+      u0 = g = e = 0.0f;
+    }
+  };
 #pragma unroll
-  for (int j = 0; j < 8; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+  for (int j = 0; j < 8 + PF; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    if (z0 + j < z1) load_pt(z0 + j, p0[j], pl[j], pw[j], pg[j], pe[j]);
 
-  for (int zb = z0; zb < z1; zb += 9) {
+  for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < W; ++r) {
       const int z = zb + r;
       if (z >= z1) break;
-      const int s8 = (r + 8) % 9, s4 = (r + 4) % 9;
-      load_rows(z + 4, uc[s8], uh[s8], lc[s8], lh[s8]);
-      const float cu = uc[s4], cl = lc[s4];
-      ldsU[kRadius + lane] = cu;
-      ldsL[kRadius + lane] = cl;
-      if (lane < 4) {
-        ldsU[lane] = uh[s4];
-        ldsL[lane] = lh[s4];
-      } else if (lane < 8) {
-        ldsU[kWave + lane] = uh[s4];
-        ldsL[kWave + lane] = lh[s4];
+      if (z + PF < z1) {
+        const int s = (r + 8 + PF) % W, q = (r + PF) % R;
+        load_rows(z + 4 + PF, uc[s], uh[s], lc[s], lh[s]);
+        load_pt(z + PF, p0[q], pl[q], pw[q], pg[q], pe[q]);
       }
+      const int ctr = (r + 4) % W;
+      const float cu = uc[ctr], cl = lc[ctr];
+      lds_put(ldsU, lane, cu, uh[ctr]);
+      lds_put(ldsL, lane, cl, lh[ctr]);
       wave_lds_fence();
-      float lapL = 0.0f;
-#pragma unroll
-      for (int k = 4; k >= 1; --k) {
-        const float sz = lc[(r + 4 - k) % 9] + lc[(r + 4 + k) % 9];
-        const float sx = ldsL[kRadius + lane - k] + ldsL[kRadius + lane + k];
-        lapL = fmaf(ck(k), fmaf(-4.0f, cl, sz + sx), lapL);
-      }
-      const bool mrow = z >= d.N && z < d.N + d.nz;
-      float lapU = 0.0f;
-      if (mrow) {
-#pragma unroll
-        for (int k = 4; k >= 1; --k) {
-          const float sz = uc[(r + 4 - k) % 9] + uc[(r + 4 + k) % 9];
-          const float sx = ldsU[kRadius + lane - k] + ldsU[kRadius + lane + k];
-          lapU = fmaf(ck(k), fmaf(-4.0f, cu, sz + sx), lapU);
-        }
-      }
+      const Row row = make_row(d, z);
+      float lapL = laplace<W>(lc, r + 4, ldsL, lane);
+      const float lapU0 = row.model ? laplace<W>(uc, r + 4, ldsU, lane) : 0.0f;
       wave_lds_fence();
       int tr = -1;
       if (z == rz) {
@@ -363,32 +426,25 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
         rz = rp < rend ? a.rrows[rp].z : INT_MAX;
       }
       if (tr >= 0) lapL += psi[tr];
-      if (src_tile && z == sd.src_z && xs == sd.src_xs) lapU += fsrc;
+      float lapU = lapU0;
+      if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lapU += fsrc;
 
-      if (xin) {
-        const int64_t idx = (int64_t)z * d.P + xs;
-        const float wv_ = a.w[idx];
-        const float l2 = l_p2[idx];
-        const int dz = max(max(d.N - z, z - (d.N + d.nz - 1)), 0);
-        const int dd = max(dz, dxs);
-        float lout;
-        if (dd == 0) {
-          lout = fmaf(wv_, lapL, 2.0f * cl - l2);
-        } else {
-          const double gm = a.sp_a * (double)(dd * dd);
-          lout = (float)((2.0 * (double)cl - (1.0 - gm) * (double)l2 + (double)wv_ * (double)lapL) /
-                         (1.0 + gm));
-        }
+      if (col.xin) {
+        const int q = r % R;
+        const int64_t idx = (int64_t)z * d.P + col.xs;
+        const float wv_ = pw[q];
+        const int dd = max(row.dz, col.dxs);
+        const float lout =
+            dd == 0 ? fmaf(wv_, lapL, 2.0f * cl - pl[q]) : sponge_update(a.sp_a, dd, cl, pl[q], wv_, lapL);
         l_p2[idx] = lout;
         if (dd == 0) {
-          const int64_t mi = (int64_t)(z - d.N) * d.nx + mx;
-          const float u0 = reset ? snap0[mi] : (reset_prev ? snapp[mi] : u_m[idx]);
+          const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
           const float D = wv_ * lapU;
-          u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - u0);
-          G[mi] = fmaf(lout, D, G[mi]);
-          E[mi] = first ? D * D : fmaf(D, D, E[mi]);
+          u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - p0[q]);
+          G[mi] = fmaf(lout, D, pg[q]);
+          E[mi] = fmaf(D, D, pe[q]);
         } else {
-          const int ri = ring_index(d, z, x);
+          const int ri = strip_index(row, col);
           if (ri >= 0) u_m[idx] = strip ? strip[ri] : 0.0f;
         }
       }
@@ -635,22 +691,37 @@ hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const S
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const StepArgs& a, int flags, hipStream_t s) {
+template <int PF>
+static hipError_t launch_forward_pf(const StepArgs& a, int flags, hipStream_t s) {
   const dim3 grid(step_blocks(a.d, a.S)), block(256);
   switch (flags) {
-    case 0: hipLaunchKernelGGL(k_forward<0>, grid, block, 0, s, a); break;
-    case kFwdRecord: hipLaunchKernelGGL(k_forward<kFwdRecord>, grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_forward<0, PF>), grid, block, 0, s, a); break;
+    case kFwdRecord: hipLaunchKernelGGL((k_forward<kFwdRecord, PF>), grid, block, 0, s, a); break;
     case kFwdRecord | kFwdCkpt:
-      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt, PF>), grid, block, 0, s, a);
       break;
-    case kFwdIllum: hipLaunchKernelGGL(k_forward<kFwdIllum>, grid, block, 0, s, a); break;
+    case kFwdIllum: hipLaunchKernelGGL((k_forward<kFwdIllum, PF>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_reverse(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reverse, dim3(step_blocks(a.d, a.S)), dim3(256), 0, s, a);
+hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s) {
+  switch (prefetch) {
+    case 1: return launch_forward_pf<1>(a, flags, s);
+    case 3: return launch_forward_pf<3>(a, flags, s);
+    case 7: return launch_forward_pf<7>(a, flags, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reverse(const StepArgs& a, int prefetch, hipStream_t s) {
+  const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  switch (prefetch) {
+    case 1: hipLaunchKernelGGL(k_reverse<1>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_reverse<3>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -128,6 +128,7 @@ struct Plan {
   int nshot = 0, ntrace = 0, max_nrec = 0, nt_max = 0;
   int S = 1, nbatch = 0, ncs = 0;
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
+  int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
   double sp_a = 0.0;
   float dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -150,7 +151,7 @@ struct Plan {
 };
 
 struct ExecChoice {
-  int S, TZ, graph_steps;
+  int S, TZ, graph_steps, pf_fwd, pf_rev;
 };
 
 std::mutex g_mutex;
@@ -225,6 +226,8 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->S = plain ? 1 : std::max(1, std::min(ex.S, std::max(geo->nshot, 1)));
   p->graph_steps = plain ? -1 : ex.graph_steps;
   p->xcd_map = (p->S >= 8 && p->S % 8 == 0) ? 1 : 0;
+  p->pf_fwd = ex.pf_fwd;
+  p->pf_rev = ex.pf_rev;
   build_dims(*p, g, ex.TZ);
   const Dims& d = p->d;
   const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
@@ -375,7 +378,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   if (nsteps <= 0) return FWI_OK;
   StepArgs a = step_args(p, ws, batch, wavelet, wstride);
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
-    return phase == kPhaseFwd ? launch_forward(args, flags, s) : launch_reverse(args, s);
+    return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s) : launch_reverse(args, p.pf_rev, s);
   };
   const int T = p.graph_steps;
   if (T <= 0) {
@@ -387,6 +390,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   }
   int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
   const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
+                                      (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
                                       (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
                                       (uint64_t)wstride};
   hipGraphExec_t exec = nullptr;
@@ -547,32 +551,47 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
              hipStream_t s, ExecChoice& best) {
   const int ns = geo->nshot;
   const int Smax = best.S;
-  std::vector<int> Ss, TZs;
+  std::vector<int> Ss, TZs, PFs;
   if (ex && ex->shots_in_flight > 0) Ss = {ex->shots_in_flight};
   else
     for (int c : {8, 16, 32, 64})
       if (c <= Smax) Ss.push_back(c);
   if (Ss.empty()) Ss = {Smax};
   if (ex && ex->tile_rows > 0) TZs = {ex->tile_rows};
-  else TZs = {32, 64, 128};
+  else TZs = {16, 32, 64, 128};
+  if (ex && ex->prefetch > 0) PFs = {ex->prefetch};
+  else PFs = {1, 3, 7};
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD);
+  const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
+  const int nsteps = 8;
+  // forward and reverse sweeps are tuned separately for each (S, TZ); the
+  // score is the time of one forward plus one reverse step per shot
   double best_rate = -1.0;
   ExecChoice choice = best;
   for (int S : Ss) {
     for (int TZ : TZs) {
-      ExecChoice c{S, TZ, best.graph_steps};
+      ExecChoice c{S, TZ, best.graph_steps, PFs[0], std::min(PFs[0], 3)};
       auto p = build_plan(g, geo, c, 0, what, 0);
       if (p->L.total > ws_bytes) continue;
       if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
       HIP_TRY(launch_fill(at<char>(ws, p->L.u), p->L.g - p->L.u, s));
-      const int nsteps = 8;
-      const int shots = std::min(S, ns);
-      double ms = time_steps(*p, ws, kFwdRecord, kPhaseFwd, nsteps, wavelet, wstride, s);
-      if (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD)
-        ms += 2.75 * time_steps(*p, ws, 0, kPhaseRev, nsteps, wavelet, wstride, s);
-      const double rate = (double)shots / ms;
+      double fbest = 1e30, rbest = grad ? 1e30 : 0.0;
+      int fpf = c.pf_fwd, rpf = c.pf_rev;
+      for (int pf : PFs) {
+        p->pf_fwd = pf;
+        const double ms = time_steps(*p, ws, fwd_flags, kPhaseFwd, nsteps, wavelet, wstride, s);
+        if (ms < fbest) { fbest = ms; fpf = pf; }
+        if (grad && pf <= 3) {
+          p->pf_rev = pf;
+          const double mr = time_steps(*p, ws, 0, kPhaseRev, nsteps, wavelet, wstride, s);
+          if (mr < rbest) { rbest = mr; rpf = pf; }
+        }
+      }
+      const int shots = std::min(S, std::max(ns, 1));
+      const double rate = (double)shots / (fbest + rbest);
       if (rate > best_rate) {
         best_rate = rate;
-        choice = c;
+        choice = ExecChoice{S, TZ, best.graph_steps, fpf, rpf};
       }
     }
   }
@@ -592,6 +611,9 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.S = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : default_shots_in_flight(geo->nshot);
   c.TZ = (ex && ex->tile_rows > 0) ? ex->tile_rows : default_tile_rows(Z);
   c.graph_steps = (ex && ex->graph_steps != 0) ? ex->graph_steps : 32;
+  const int pf = (ex && ex->prefetch > 0) ? ex->prefetch : 0;
+  c.pf_fwd = pf ? pf : 3;
+  c.pf_rev = pf ? std::min(pf, 3) : 1;
   return c;
 }
 
@@ -600,7 +622,7 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   h.pod(*g);
   h.pod(geo->nshot);
   std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
-                             (uint64_t)(ex ? ex->tile_rows : 0)};
+                             (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -625,6 +647,8 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   if (ex && (ex->shots_in_flight < 0 || ex->tile_rows < 0 || ex->graph_steps < -1))
     return fail(FWI_ERR_ARG, "bad exec settings");
   if (ex && ex->tile_rows > 0 && ex->tile_rows < 8) return fail(FWI_ERR_ARG, "tile_rows must be >= 8");
+  if (ex && ex->prefetch != 0 && ex->prefetch != 1 && ex->prefetch != 3 && ex->prefetch != 7)
+    return fail(FWI_ERR_ARG, "prefetch must be 0, 1, 3 or 7");
   ExecChoice c = base_choice(g, geo, ex);
   const bool tune = !plain && ex && ex->autotune && !sizing_only;
   const uint64_t ikey = inputs_hash(g, geo);
@@ -654,6 +678,8 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.S);
   h.pod(c.TZ);
   h.pod(c.graph_steps);
+  h.pod(c.pf_fwd);
+  h.pod(c.pf_rev);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
     if ((*it)->key == key) {
@@ -700,6 +726,28 @@ extern "C" {
 const char* fwi_last_error(void) { return g_last_error.c_str(); }
 
 int fwi_validate(const fwi_grid* grid, const fwi_geometry* geom) { return check_inputs(grid, geom); }
+
+int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, int what,
+                   fwi_exec* chosen) {
+  int rc = check_inputs(grid, geom);
+  if (rc) return rc;
+  if (!chosen) return fail(FWI_ERR_ARG, "chosen must not be NULL");
+  if (what < FWI_WS_FORWARD || what > FWI_WS_AUTOGRAD) return fail(FWI_ERR_ARG, "bad `what`");
+  const int plain = exec && exec->mode == FWI_EXEC_PLAIN;
+  ExecChoice c = base_choice(grid, geom, exec);
+  if (!plain && exec && exec->autotune) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto it = g_tuned.find(tune_key(grid, geom, exec, what));
+    if (it != g_tuned.end()) c = it->second;
+  }
+  chosen->mode = exec ? exec->mode : FWI_EXEC_BATCHED;
+  chosen->autotune = exec ? exec->autotune : 0;
+  chosen->shots_in_flight = plain ? 1 : std::max(1, std::min(c.S, std::max(geom->nshot, 1)));
+  chosen->tile_rows = c.TZ;
+  chosen->graph_steps = plain ? -1 : c.graph_steps;
+  chosen->prefetch = c.pf_fwd;
+  return FWI_OK;
+}
 
 size_t fwi_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, int what,
                            int hmax) {

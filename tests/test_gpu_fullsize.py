@@ -18,17 +18,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "golden"))
 import make_golden  # noqa: E402
 
+from helpers import GRAD_TOL, TRACE_TOL, rel, report
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-TRACE_TOL = 1e-4
-GRAD_TOL = 1e-3
-
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def golden(name):
@@ -40,15 +33,17 @@ def golden(name):
     return z, w, grid, geom, wav, d_obs
 
 
-def check(z, J, g, H1, traces, mult=1.0, D=None):
+def check(tag, z, J, g, H1, traces, mult=1.0, D=None):
+    """The stored residual is well conditioned (recorded data = 0.3 x RMS
+    noise), so J is held to the seismogram tolerance."""
     zs, rs, ts = int(z["zs"]), int(z["rs"]), int(z["ts"])
-    assert abs(J - mult * float(z["J"])) <= TRACE_TOL * mult * float(z["J"])
-    assert rel(g[::zs, ::zs], mult * z["g"]) < GRAD_TOL
-    assert rel(H1[::zs, ::zs], mult * z["H1"]) < GRAD_TOL
     ntr = z["traces"].shape[0]
-    assert rel(traces[::rs, ::ts][:ntr], z["traces"]) < TRACE_TOL
+    assert report(f"{tag} traces", rel(traces[::rs, ::ts][:ntr], z["traces"]), TRACE_TOL) < TRACE_TOL
+    assert report(f"{tag} J", abs(J - mult * float(z["J"])) / (mult * float(z["J"])), TRACE_TOL) <= TRACE_TOL
+    assert report(f"{tag} grad", rel(g[::zs, ::zs], mult * z["g"]), GRAD_TOL) < GRAD_TOL
+    assert report(f"{tag} H1", rel(H1[::zs, ::zs], mult * z["H1"]), GRAD_TOL) < GRAD_TOL
     if D is not None:
-        assert rel(D[::4, ::zs, ::zs], mult * z["D"]) < GRAD_TOL
+        assert report(f"{tag} D", rel(D[::4, ::zs, ::zs], mult * z["D"]), GRAD_TOL) < GRAD_TOL
 
 
 @pytest.mark.parametrize("S,TZ", [(8, 64), (8, 32), (8, 128), (4, 64)])
@@ -65,7 +60,8 @@ def test_layered_1024x384_short_record(S, TZ):
     rs = int(z["rs"])
     nrec = geom2.rec_ptr[1]
     both = np.concatenate([tr[0:nrec:rs], tr[nrec:2 * nrec:rs]])
-    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), np.repeat(both, rs, axis=0), mult=4.0)
+    check(f"layered nt400 S{S} TZ{TZ}", z, float(J), g.cpu().numpy(), H1.cpu().numpy(),
+          np.repeat(both, rs, axis=0), mult=4.0)
 
 
 @pytest.mark.parametrize("mode", ["batched", "plain"])
@@ -74,7 +70,7 @@ def test_layered_1024x384_full_record(mode):
     ex = B.make_exec(mode=B.EXEC_PLAIN) if mode == "plain" else B.make_exec(autotune=1)
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
-    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr)
+    check(f"layered nt4000 {mode}", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr)
 
 
 def test_layered_2048x768_full_record_offset_diag():
@@ -82,4 +78,4 @@ def test_layered_2048x768_full_record_offset_diag():
     ex = B.make_exec(autotune=1)
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, D = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex, hmax=int(z["hmax"]))
-    check(z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr, D=D.cpu().numpy())
+    check("layered 2048x768 nt8000", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr, D=D.cpu().numpy())

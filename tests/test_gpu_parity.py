@@ -1,8 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Tolerances (relative L2): 1e-4 on seismograms, 1e-3 on gradients and
-Hessian diagonals, as the spec accuracy contract states.  J is checked
-to 1e-4 (it is a sum of squares of the seismogram residual).
+Hessian diagonals; J to the tolerance its seismograms imply (tests/helpers.py).
 """
 import numpy as np
 import pytest
@@ -12,18 +11,11 @@ from paper_1406_1864_amd import binding as B
 from paper_1406_1864_amd.synthetic import (Geometry, Grid, anomaly_200x100, gaussian_anomaly, ricker,
                                            tiny_24x16, random_traces)
 
+from helpers import GRAD_TOL, TRACE_TOL, j_tolerance, rel, report
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-TRACE_TOL = 1e-4
-GRAD_TOL = 1e-3
-
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def cpu(t):
@@ -73,7 +65,7 @@ def test_forward_tiny(name):
     w = tiny_24x16(nt=300)
     ref = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
     got = cpu(B.forward(w.v_true, w.wavelet, w.grid, w.geom, EXECS[name]))
-    assert rel(got, ref) < TRACE_TOL
+    assert report(f"forward tiny {name}", rel(got, ref), TRACE_TOL) < TRACE_TOL
 
 
 @pytest.mark.parametrize("name", list(EXECS))
@@ -84,7 +76,7 @@ def test_forward_ragged(name):
     for s in range(geom.nshot):
         a, b = geom.rec_ptr[s], geom.rec_ptr[s + 1]
         if b > a and np.any(ref[a:b] != 0):
-            assert rel(got[a:b], ref[a:b]) < TRACE_TOL, s
+            assert report(f"forward ragged {name} shot {s}", rel(got[a:b], ref[a:b]), TRACE_TOL) < TRACE_TOL
     assert np.all(got[:, 0] == 0)
     for s in range(geom.nshot):
         a, b = geom.rec_ptr[s], geom.rec_ptr[s + 1]
@@ -95,7 +87,7 @@ def test_forward_anomaly_full():
     w = anomaly_200x100()
     ref = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
     got = cpu(B.forward(w.v_true, w.wavelet, w.grid, w.geom))
-    assert rel(got, ref) < TRACE_TOL
+    assert report("forward anomaly 200x100", rel(got, ref), TRACE_TOL) < TRACE_TOL
 
 
 # ------------------------------------------------------------------ gradient
@@ -107,6 +99,7 @@ def anomaly_ref():
     for kind in ("int", "l2"):
         J, g, H1, E = oracle.gradient(w.v_start, w.grid, w.geom, w.wavelet, d_obs, kind, return_parts=True)
         out[kind] = (J, g, H1, E)
+    out["syn"] = oracle.forward_traces(w.v_start, w.grid, w.geom, w.wavelet)
     return w, d_obs, out
 
 
@@ -115,9 +108,10 @@ def test_gradient_anomaly_full(anomaly_ref, kind):
     w, d_obs, ref = anomaly_ref
     J, g, H1, _ = ref[kind]
     Jg, gg, Hg, _ = B.gradient(w.v_start, w.wavelet, w.grid, w.geom, d_obs.astype(np.float32), kind)
-    assert abs(float(Jg) - J) <= TRACE_TOL * J
-    assert rel(cpu(gg), g) < GRAD_TOL
-    assert rel(cpu(Hg), H1) < GRAD_TOL
+    jt = j_tolerance(ref["syn"], d_obs, kind, w.grid.dt)
+    assert report(f"J anomaly {kind}", abs(float(Jg) - J) / J, jt) <= jt
+    assert report(f"grad anomaly {kind}", rel(cpu(gg), g), GRAD_TOL) < GRAD_TOL
+    assert report(f"H1 anomaly {kind}", rel(cpu(Hg), H1), GRAD_TOL) < GRAD_TOL
 
 
 @pytest.mark.parametrize("rcv", ["pm", "none"])
@@ -131,19 +125,19 @@ def test_offset_diagonal_anomaly_full(anomaly_ref, rcv):
                              rcv_model=rcv)
     Dg = cpu(Dg)
     for h in range(2 * H + 1):
-        assert rel(Dg[h], Dref[h]) < GRAD_TOL, h
+        assert report(f"D anomaly {rcv} h={h - H}", rel(Dg[h], Dref[h]), GRAD_TOL) < GRAD_TOL, h
 
 
 def test_hessian_diag_forward_only(anomaly_ref):
     w, _, ref = anomaly_ref
     _, _, H1, E = ref["int"]
     got = cpu(B.hessian_diag(w.v_start, w.wavelet, w.grid, w.geom, B.HESS_EQ1))
-    assert rel(got, H1) < GRAD_TOL
+    assert report("H1 forward-only", rel(got, H1), GRAD_TOL) < GRAD_TOL
     H = 3
     A = [oracle.aperture_factor(w.grid, *w.geom.shot(0)[2:4])]
     Dref = oracle.offset_diag(w.v_start, E, A, H)
     Dg = cpu(B.hessian_diag(w.v_start, w.wavelet, w.grid, w.geom, B.HESS_OFFSET, hmax=H))
-    assert rel(Dg, Dref) < GRAD_TOL
+    assert report("D forward-only", rel(Dg, Dref), GRAD_TOL) < GRAD_TOL
 
 
 @pytest.mark.parametrize("name", list(EXECS))
@@ -157,10 +151,13 @@ def test_gradient_ragged(name, kind):
          else np.zeros((grid.nz, grid.nx)) for s in range(geom.nshot)]
     Dref = oracle.offset_diag(v_start, E, A, H)
     Jg, gg, Hg, Dg = B.gradient(v_start, wav, grid, geom, d_obs.astype(np.float32), kind, EXECS[name], hmax=H)
-    assert abs(float(Jg) - J) <= TRACE_TOL * J
-    assert rel(cpu(gg), g) < GRAD_TOL
-    assert rel(cpu(Hg), H1) < GRAD_TOL
-    assert rel(cpu(Dg), Dref) < GRAD_TOL
+    syn = oracle.forward_traces(v_start, grid, geom, wav)
+    jt = j_tolerance(syn, d_obs, kind, grid.dt)
+    tag = f"ragged {kind} {name}"
+    assert report(f"J {tag}", abs(float(Jg) - J) / J, jt) <= jt
+    assert report(f"grad {tag}", rel(cpu(gg), g), GRAD_TOL) < GRAD_TOL
+    assert report(f"H1 {tag}", rel(cpu(Hg), H1), GRAD_TOL) < GRAD_TOL
+    assert report(f"D {tag}", rel(cpu(Dg), Dref), GRAD_TOL) < GRAD_TOL
 
 
 def test_gradient_is_deterministic():
@@ -208,8 +205,8 @@ def test_precondition_matches_oracle(anomaly_ref):
     gt = torch.as_tensor(g.astype(np.float32), device="cuda")
     out = B.precondition(v, gt, torch.as_tensor(H1.astype(np.float32), device="cuda"), w.grid, B.PRECOND_SHOT)
     ref_s = oracle.precondition(g.astype(np.float32), oracle.shot_scaling(w.v_start, H1.astype(np.float32)))
-    assert rel(cpu(out), ref_s) < 1e-5
+    assert report("precondition shot", rel(cpu(out), ref_s), 1e-5) < 1e-5
     out = B.precondition(v, gt, torch.as_tensor(D.astype(np.float32), device="cuda"), w.grid, B.PRECOND_OFFSET,
                          hmax=H)
     ref_o = oracle.precondition(g.astype(np.float32), oracle.offset_scaling(D.astype(np.float32)))
-    assert rel(cpu(out), ref_o) < 1e-5
+    assert report("precondition offset", rel(cpu(out), ref_o), 1e-5) < 1e-5
