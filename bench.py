@@ -39,8 +39,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=150, help="time steps of the oracle sample")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="run one 1 GiB device copy first (reference for HBM counters)")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="shorten every record to NT samples (counter-collection runs; 0 = full)")
+    ap.add_argument("--exec", type=str, default="",
+                    help="pin the launch configuration instead of autotuning: "
+                         "S,TZ,graph_steps,prefetch,prefetch_reverse")
     return ap.parse_args()
 
 
@@ -73,15 +76,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kname, bytes_per_launch):
-    """Per-launch HBM bytes from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+def measured_traffic(kname, chosen):
+    """HBM bytes per launch of `kname` from the committed rocprofv3 counter
+    summary (FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy), or None when that
+    summary was taken on other kernel source or another launch configuration."""
     path = os.path.join(ROOT, "profiles", f"{kname}_pmc_layered_1024x384.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         p = json.load(fh)
     if p.get("kernel_source_sha") != kernel_hash():
+        return None
+    if any(p["launch_config"].get(k) != chosen.get(k) for k in p["launch_config"]):
         return None
     return p.get("bytes_per_launch")
 
@@ -120,17 +126,30 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     B.load()
-    if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    # a plain 1 GiB device-to-device copy: reference for the HBM counters and
+    # the practically reachable streaming bandwidth on this GPU
+    ca = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    ca.fill_(1.0)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
 
     w = layered_1024x384()
     if args.shots != w.geom.nshot:
         w.geom = w.geom.subset(range(args.shots))
+    if args.nt:
+        from paper_1406_1864_amd.synthetic import Grid
+        w.geom = w.geom.with_nt(args.nt)
+        w.grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, args.nt, w.grid.nsponge, w.grid.v_ref)
+        w.wavelet = w.wavelet[:args.nt]
     grid, geom = w.grid, w.geom
     HM = 16
     print(f"# workload {w.name}: {geom.nshot} shots, grid {grid.nz}x{grid.nx}, nt {grid.nt_max}", file=sys.stderr,
@@ -138,7 +157,13 @@ def main():
 
     # recorded data: modelled from the true model with the same engine
     d_obs = B.forward(w.v_true, w.wavelet, grid, geom, B.make_exec(), device=dev)
-    ex = B.make_exec(autotune=1)
+    torch.cuda.synchronize()
+    print("# recorded data modelled", file=sys.stderr, flush=True)
+    if args.exec:
+        S_, TZ_, G_, PF_, PR_ = (int(x) for x in args.exec.split(","))
+        ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_)
+    else:
+        ex = B.make_exec(autotune=1)
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
     v = torch.tensor(w.v_start, device=dev, requires_grad=True)
 
@@ -167,7 +192,8 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    print("# warmup done", file=sys.stderr, flush=True)
+    print("# warmup done; launch configuration:", B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD),
+          file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -189,8 +215,8 @@ def main():
     fwd_K = int(np.ceil(np.sqrt(nt.max())))
     fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
                           for s in range(shots)))
-    traffic = measured_traffic("k_reverse", None)
     chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
+    traffic = measured_traffic("k_reverse", chosen) if shots == 64 else None
     out = {
         "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
         "value": value,
@@ -204,17 +230,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name if shots == 64 else f"{w.name} ({shots} shots)", "shots": shots,
+        "config": {"workload": w.name if (shots == 64 and not args.nt) else f"{w.name} ({shots} shots, nt {grid.nt_max})",
+                   "shots": shots,
                    "grid": [grid.nz, grid.nx], "padded": [Z, X], "nt": int(nt.max()), "receivers_per_shot": 512,
                    "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned",
                    "shots_in_flight": chosen["shots_in_flight"], "tile_rows": chosen["tile_rows"],
-                   "graph_steps": chosen["graph_steps"]},
+                   "graph_steps": chosen["graph_steps"], "prefetch": chosen["prefetch"],
+                   "prefetch_reverse": chosen["prefetch_reverse"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},
         "roofline": {"bound": "hbm", "kernel": "k_reverse", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_shot_step": reverse_bytes_per_shot_step(grid, 512)},
+                     "algorithmic_bytes_per_launch": reverse_bytes_per_shot_step(grid, 512) *
+                     min(shots, chosen["shots_in_flight"])},
+        "copy_GBps": copy_gbs,
         "forward_roofline": {"achieved": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9, "unit": "GB/s",
                              "frac": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }

@@ -104,9 +104,9 @@ typedef struct {
                                  -1 = do not use graphs                        */
     int32_t autotune;         /* 1 = pick unset fields by timing (cached per
                                  grid/geometry); 0 = heuristic defaults        */
-    int32_t prefetch;         /* rows of loads a wavefront keeps in flight ahead
-                                 of its z sweep: 1, 3 or 7 (reverse kernel: 1
-                                 or 3, larger values use 3)                    */
+    int32_t prefetch;         /* rows of loads a forward-sweep wavefront keeps
+                                 in flight ahead of its z sweep: 1, 3 or 7     */
+    int32_t prefetch_reverse; /* same for the fused reverse sweep: 1 or 3      */
 } fwi_exec;
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
@@ -131,7 +131,8 @@ enum { FWI_WS_FORWARD = 0, FWI_WS_GRADIENT = 1, FWI_WS_HESSIAN = 2,
 size_t fwi_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
                            const fwi_exec *exec, int what, int hmax);
 
-/* The execution settings (shots_in_flight, tile_rows, graph_steps, prefetch) that a
+/* The execution settings (shots_in_flight, tile_rows, graph_steps, prefetch,
+ * prefetch_reverse) that a
  * call with these arguments uses: the autotuned choice once tuning has run on
  * the current device, else the heuristic defaults.  Fills *chosen (mode and
  * autotune copied from exec).  Returns 0 or FWI_ERR_*. */

@@ -559,8 +559,11 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   if (Ss.empty()) Ss = {Smax};
   if (ex && ex->tile_rows > 0) TZs = {ex->tile_rows};
   else TZs = {16, 32, 64, 128};
+  std::vector<int> RFs;
   if (ex && ex->prefetch > 0) PFs = {ex->prefetch};
   else PFs = {1, 3, 7};
+  if (ex && ex->prefetch_reverse > 0) RFs = {ex->prefetch_reverse};
+  else RFs = {1, 3};
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
   const int nsteps = 8;
@@ -570,7 +573,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   ExecChoice choice = best;
   for (int S : Ss) {
     for (int TZ : TZs) {
-      ExecChoice c{S, TZ, best.graph_steps, PFs[0], std::min(PFs[0], 3)};
+      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0]};
       auto p = build_plan(g, geo, c, 0, what, 0);
       if (p->L.total > ws_bytes) continue;
       if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
@@ -581,11 +584,11 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
         p->pf_fwd = pf;
         const double ms = time_steps(*p, ws, fwd_flags, kPhaseFwd, nsteps, wavelet, wstride, s);
         if (ms < fbest) { fbest = ms; fpf = pf; }
-        if (grad && pf <= 3) {
-          p->pf_rev = pf;
-          const double mr = time_steps(*p, ws, 0, kPhaseRev, nsteps, wavelet, wstride, s);
-          if (mr < rbest) { rbest = mr; rpf = pf; }
-        }
+      }
+      for (int pf : (grad ? RFs : std::vector<int>{})) {
+        p->pf_rev = pf;
+        const double mr = time_steps(*p, ws, 0, kPhaseRev, nsteps, wavelet, wstride, s);
+        if (mr < rbest) { rbest = mr; rpf = pf; }
       }
       const int shots = std::min(S, std::max(ns, 1));
       const double rate = (double)shots / (fbest + rbest);
@@ -611,9 +614,8 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.S = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : default_shots_in_flight(geo->nshot);
   c.TZ = (ex && ex->tile_rows > 0) ? ex->tile_rows : default_tile_rows(Z);
   c.graph_steps = (ex && ex->graph_steps != 0) ? ex->graph_steps : 32;
-  const int pf = (ex && ex->prefetch > 0) ? ex->prefetch : 0;
-  c.pf_fwd = pf ? pf : 3;
-  c.pf_rev = pf ? std::min(pf, 3) : 1;
+  c.pf_fwd = (ex && ex->prefetch > 0) ? ex->prefetch : 3;
+  c.pf_rev = (ex && ex->prefetch_reverse > 0) ? ex->prefetch_reverse : 1;
   return c;
 }
 
@@ -622,7 +624,8 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   h.pod(*g);
   h.pod(geo->nshot);
   std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
-                             (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0)};
+                             (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0),
+                             (uint64_t)(ex ? ex->prefetch_reverse : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -649,6 +652,8 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   if (ex && ex->tile_rows > 0 && ex->tile_rows < 8) return fail(FWI_ERR_ARG, "tile_rows must be >= 8");
   if (ex && ex->prefetch != 0 && ex->prefetch != 1 && ex->prefetch != 3 && ex->prefetch != 7)
     return fail(FWI_ERR_ARG, "prefetch must be 0, 1, 3 or 7");
+  if (ex && ex->prefetch_reverse != 0 && ex->prefetch_reverse != 1 && ex->prefetch_reverse != 3)
+    return fail(FWI_ERR_ARG, "prefetch_reverse must be 0, 1 or 3");
   ExecChoice c = base_choice(g, geo, ex);
   const bool tune = !plain && ex && ex->autotune && !sizing_only;
   const uint64_t ikey = inputs_hash(g, geo);
@@ -746,6 +751,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   chosen->tile_rows = c.TZ;
   chosen->graph_steps = plain ? -1 : c.graph_steps;
   chosen->prefetch = c.pf_fwd;
+  chosen->prefetch_reverse = c.pf_rev;
   return FWI_OK;
 }
 
