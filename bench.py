@@ -61,11 +61,14 @@ def reverse_bytes_per_shot_step(grid, nrec):
 
 
 def forward_bytes_per_shot_step(grid, nrec, K):
+    """Forward step in increment form: read u[n], d[n], w; write u[n+1],
+    d[n+1] (20 B per padded cell); strip ring 4 B; snapshot pair every K
+    steps 8 B per model cell; receivers 4 B."""
     nz, nx, N = grid.nz, grid.nx, grid.nsponge
     model = nz * nx
     padded = (nz + 2 * N) * (nx + 2 * N)
     ring = 8 * (nz + nx)
-    return 16 * padded + 4 * ring + 8 * model / K + 4 * nrec
+    return 20 * padded + 4 * ring + 8 * model / K + 4 * nrec
 
 
 def kernel_hash():

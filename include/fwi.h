@@ -71,13 +71,16 @@ extern "C" {
 #define FWI_CFL_LIMIT 0.5546324796655889
 
 /* ---------------------------------------------------------------- inputs */
+/* dx, dt and v_ref are doubles: a time step such as 1 ms is not a float, and
+ * a rounded dt enters every update through dt^2 v^2 / h^2 as a systematic
+ * velocity bias (relative 1e-7) whose phase error grows with record length. */
 typedef struct {
     int32_t nz, nx;     /* model cells (rows, columns)                         */
-    float   dx;         /* grid spacing h in metres (dz == dx)                 */
-    float   dt;         /* time step in seconds                                */
+    double  dx;         /* grid spacing h in metres (dz == dx)                 */
+    double  dt;         /* time step in seconds                                */
     int32_t nt_max;     /* trace length / stride of wavelet and data rows      */
     int32_t nsponge;    /* sponge width N in cells, >= 4                       */
-    float   v_ref;      /* sponge reference velocity (m/s), also the declared
+    double  v_ref;      /* sponge reference velocity (m/s), also the declared
                            maximum velocity used for the CFL check             */
 } fwi_grid;
 

@@ -53,8 +53,8 @@ class FwiError(RuntimeError):
 
 
 class fwi_grid(ctypes.Structure):
-    _fields_ = [("nz", c_int32), ("nx", c_int32), ("dx", c_float), ("dt", c_float),
-                ("nt_max", c_int32), ("nsponge", c_int32), ("v_ref", c_float)]
+    _fields_ = [("nz", c_int32), ("nx", c_int32), ("dx", c_double), ("dt", c_double),
+                ("nt_max", c_int32), ("nsponge", c_int32), ("v_ref", c_double)]
 
 
 class fwi_geometry(ctypes.Structure):

@@ -16,6 +16,9 @@ namespace fwi {
 constexpr int kWave = 64;         // CDNA wavefront width == tile width in x
 constexpr int kWavesPerBlock = 4;  // independent wavefronts per workgroup
 constexpr int kRadius = 4;         // stencil half-width (8th order)
+// levels per checkpoint set of the source wavefield: u (two time levels) and
+// the forward sweep's increment d[n] = u[n] - u[n-1]
+constexpr int kULevels = 3;
 
 struct Dims {
   int32_t nz, nx, N;     // model rows / columns, sponge width
@@ -61,7 +64,7 @@ struct StepArgs {
   const RmapRow* rrows;
   const int32_t* rmaps;
   const float* w;       // dt^2 v^2 / h^2 on the padded grid (storage layout)
-  float* u;             // [cs][2][field]   source wavefield, two time levels
+  float* u;             // [cs][3][field]   u[n] at level n & 1, increment at level 2
   float* lam;           // [slot][2][field] adjoint wavefield
   float* g;             // [slot][model]    sum_m lam[m] D[m]
   float* E;             // [slot][model]    sum_m D[m]^2
@@ -107,7 +110,7 @@ struct EpiArgs {
 };
 
 // host-side launchers (fwi_kernels.hip)
-hipError_t launch_prep(const Dims& d, const float* v, float* w, float dt, float h, float vmax,
+hipError_t launch_prep(const Dims& d, const float* v, float* w, double dt, double h, float vmax,
                        int32_t* err, hipStream_t s);
 hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s);
 hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,

@@ -130,7 +130,7 @@ struct Plan {
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
   int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
   double sp_a = 0.0;
-  float dx = 0, dt = 0;
+  double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
   std::vector<SlotInfo> slots;  // [nbatch][S]
   std::vector<int> batch_nt;    // longest record of each batch
@@ -316,7 +316,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.w = take(sizeof(float) * d.field);
   L.traces = take(sizeof(float) * (size_t)g->nt_max * std::max(p->ntrace, 1));
   L.jpart = take(sizeof(double) * std::max(p->ntrace, 1));
-  L.u = take(sizeof(float) * 2 * d.field * p->ncs);
+  L.u = take(sizeof(float) * kULevels * d.field * p->ncs);
   L.lam = grad ? take(sizeof(float) * 2 * d.field * p->S) : o;
   L.g = grad ? take(sizeof(float) * d.model * p->S) : o;
   L.E = (grad || hess) ? take(sizeof(float) * d.model * p->S) : o;
@@ -457,7 +457,7 @@ int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s) {
   if (rc) return rc;
   Header* hd = at<Header>(ws, p.L.hdr);
   HIP_TRY(launch_set(&hd->err, 0, s));
-  const float vmax = (float)(FWI_CFL_LIMIT * p.dx / p.dt);
+  const float vmax = (float)(FWI_CFL_LIMIT * p.dx / p.dt);  // device check in FP32
   HIP_TRY(launch_prep(p.d, v, at<float>(ws, p.L.w), p.dt, p.dx, vmax, &hd->err, s));
   return FWI_OK;
 }
@@ -465,7 +465,7 @@ int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s) {
 int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int64_t wstride,
                   hipStream_t s) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), 2 * p.d.field, 2 * p.d.field, slots, p.S, 1, s));
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1, s));
   return run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
 }
 
@@ -479,7 +479,7 @@ int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipSt
   m.nt_max = p.nt_max;
   m.kind = misfit;
   m.dt = p.dt;
-  m.psi_scale = (double)p.dx * p.dx / ((double)p.dt * p.dt);
+  m.psi_scale = p.dx * p.dx / (p.dt * p.dt);
   m.Jpart = at<double>(ws, p.L.jpart);
   m.err = &at<Header>(ws, p.L.hdr)->err;
   HIP_TRY(launch_misfit(m, p.S, p.max_nrec, s));
@@ -506,8 +506,8 @@ int epilogue_batch(Plan& p, void* ws, int b, const float* v, float* H1, float* D
   e.D = D;
   e.hmax = D ? hmax : 0;
   e.rcv_none = (rcv_model == FWI_RCV_NONE);
-  e.h = p.dx;
-  e.inv_dt3 = (float)(1.0 / ((double)p.dt * p.dt * p.dt));
+  e.h = (float)p.dx;
+  e.inv_dt3 = (float)(1.0 / (p.dt * p.dt * p.dt));
   e.err = &at<Header>(ws, p.L.hdr)->err;
   HIP_TRY(launch_epilogue(e, s));
   return FWI_OK;
