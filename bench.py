@@ -1,13 +1,22 @@
 """Throughput of the batched, autograd FWI gradient on one MI355X.
 
-One step = the whole hot path over the 1024x384 layered workload (64 shots,
-512 receivers each, nt = 4000, dt = 1 ms, Ricker 8 Hz), inputs resident in
-HBM: model prep, forward sweep of every shot with sqrt(nt) snapshots and
-boundary strips, time-integral misfit and adjoint source (eq. (2)), the fused
-backward sweep (source-wavefield reconstruction, adjoint propagation,
-zero-lag imaging, eq. (1) illumination), the per-shot Hessian epilogue (H1 and
-the offset diagonal, |h| <= 16) and the shot-scaling preconditioned gradient,
-driven through torch.autograd (J.backward()).
+One step = the whole hot path over one batch of synthetic input, inputs
+resident in HBM: model prep, forward sweep of every shot with sqrt(nt)
+snapshots and boundary strips, time-integral misfit and adjoint source
+(eq. (2)), the fused backward sweep (source-wavefield reconstruction, adjoint
+propagation, zero-lag imaging, eq. (1) illumination), the per-shot Hessian
+epilogue and the preconditioned gradient, driven through torch.autograd
+(J.backward()).
+
+Workloads (--workload):
+  layered  (default) 1024x384 layered model, 64 shots, 512 receivers each,
+           nt = 4000, dt = 1 ms, Ricker 8 Hz; H1 and the offset diagonal
+           |h| <= 16; shot-scaling preconditioner
+  ragged   same model, 256 shots of 128..1024 receivers and nt 2000..6000; H1;
+           shot-scaling preconditioner
+  offset   2048x768 at dx = 6.25 m, 32 shots, 1024 receivers, nt = 8000,
+           dt = 0.5 ms, Ricker 15 Hz; H1 and the offset diagonal |h| <= 16;
+           sub-offset Hessian preconditioner
 
 Prints one JSON line.  `value` is shot-gradients per second; the line also
 carries Gcell-updates/s, the roofline of the dominant kernel (the fused
@@ -34,7 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots", type=int, default=64, help="shots of the workload (64 = the full workload)")
+    ap.add_argument("--workload", choices=["layered", "ragged", "offset"], default="layered")
+    ap.add_argument("--shots", type=int, default=0, help="use only the first SHOTS shots (0 = all)")
     ap.add_argument("--plain-shots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -124,7 +134,7 @@ def main():
     import torch
     from paper_1406_1864_amd import binding as B
     from paper_1406_1864_amd.autograd import FWIProblem, fwi_misfit
-    from paper_1406_1864_amd.synthetic import layered_1024x384
+    from paper_1406_1864_amd.synthetic import layered_1024x384, offset_2048x768, ragged_1024x384
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -145,8 +155,12 @@ def main():
     copy_gbs = 5 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del ca, cb
 
-    w = layered_1024x384()
-    if args.shots != w.geom.nshot:
+    make, HM, PK = {"layered": (layered_1024x384, 16, B.PRECOND_SHOT),
+                    "ragged": (ragged_1024x384, None, B.PRECOND_SHOT),
+                    "offset": (offset_2048x768, 16, B.PRECOND_OFFSET)}[args.workload]
+    w = make()
+    full_shots = w.geom.nshot
+    if args.shots and args.shots != w.geom.nshot:
         w.geom = w.geom.subset(range(args.shots))
     if args.nt:
         from paper_1406_1864_amd.synthetic import Grid
@@ -154,7 +168,6 @@ def main():
         w.grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, args.nt, w.grid.nsponge, w.grid.v_ref)
         w.wavelet = w.wavelet[:args.nt]
     grid, geom = w.grid, w.geom
-    HM = 16
     print(f"# workload {w.name}: {geom.nshot} shots, grid {grid.nz}x{grid.nx}, nt {grid.nt_max}", file=sys.stderr,
           flush=True)
 
@@ -170,6 +183,11 @@ def main():
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
     v = torch.tensor(w.v_start, device=dev, requires_grad=True)
 
+    def precond(vd, g, problem):
+        if PK == B.PRECOND_OFFSET:
+            return B.precondition(vd, g, problem.offset, grid, B.PRECOND_OFFSET, hmax=HM, device=dev)
+        return B.precondition(vd, g, problem.illum, grid, B.PRECOND_SHOT, device=dev)
+
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     phase = np.zeros(3)
 
@@ -183,7 +201,7 @@ def main():
         J.backward()
         if timed:
             ev[2].record()
-        gp = B.precondition(v.detach(), v.grad, pr.illum, grid, B.PRECOND_SHOT, device=dev)
+        gp = precond(v.detach(), v.grad, pr)
         if timed:
             ev[3].record()
             torch.cuda.synchronize()
@@ -219,7 +237,9 @@ def main():
     fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
                           for s in range(shots)))
     chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
-    traffic = measured_traffic("k_reverse", chosen) if shots == 64 else None
+    full = (shots == full_shots and not args.nt)
+    traffic = measured_traffic("k_reverse", chosen) if (args.workload == "layered" and full) else None
+    nrec_mean = float(np.mean(nrec)) if shots else 0.0
     out = {
         "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
         "value": value,
@@ -233,9 +253,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name if (shots == 64 and not args.nt) else f"{w.name} ({shots} shots, nt {grid.nt_max})",
+        "config": {"workload": w.name if full else f"{w.name} ({shots} shots, nt {grid.nt_max})",
                    "shots": shots,
-                   "grid": [grid.nz, grid.nx], "padded": [Z, X], "nt": int(nt.max()), "receivers_per_shot": 512,
+                   "grid": [grid.nz, grid.nx], "padded": [Z, X], "nt": int(nt.max()), "receivers_per_shot": nrec_mean,
                    "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned",
                    "shots_in_flight": chosen["shots_in_flight"], "tile_rows": chosen["tile_rows"],
                    "graph_steps": chosen["graph_steps"], "prefetch": chosen["prefetch"],
@@ -245,7 +265,7 @@ def main():
                      "precondition": phase[2] / args.steps},
         "roofline": {"bound": "hbm", "kernel": "k_reverse", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": reverse_bytes_per_shot_step(grid, 512) *
+                     "algorithmic_bytes_per_launch": reverse_bytes_per_shot_step(grid, int(nrec_mean)) *
                      min(shots, chosen["shots_in_flight"])},
         "copy_GBps": copy_gbs,
         "forward_roofline": {"achieved": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9, "unit": "GB/s",
@@ -264,7 +284,7 @@ def main():
             vp.grad = None
             Jp = fwi_misfit(vp, ppr)
             Jp.backward()
-            return B.precondition(vp.detach(), vp.grad, ppr.illum, grid, B.PRECOND_SHOT, device=dev)
+            return precond(vp.detach(), vp.grad, ppr)
 
         pstep()
         torch.cuda.synchronize()

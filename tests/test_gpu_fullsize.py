@@ -79,3 +79,18 @@ def test_layered_2048x768_full_record_offset_diag():
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, D = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex, hmax=int(z["hmax"]))
     check("layered 2048x768 nt8000", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr, D=D.cpu().numpy())
+
+
+def test_ragged_1024x384_extremes_batched():
+    """The shortest (nt 2013, 264 receivers) and the longest (nt 5988, 798
+    receivers) record of the 256-shot ragged workload, each repeated 4 times:
+    one batch of 8 uneven shots (sorted by record length, idle launches for the
+    short ones) in the autotuned batched launch; 4x the oracle's values."""
+    z, w, grid, geom2, wav, d2 = golden("ragged_1024x384_extremes")
+    geom = geom2.subset([0, 1] * 4)
+    d_obs = np.concatenate([d2] * 4)
+    ex = B.make_exec(autotune=1)
+    tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
+    J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
+    check("ragged extremes x4", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr[:geom2.ntrace], mult=4.0)
+    assert np.all(tr[:geom2.rec_ptr[1], int(geom2.nt[0]):] == 0)

@@ -1,0 +1,140 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in the oracle (on the CPU, through monkeypatch)
+and checks that at least one of the pins in test_oracle_pins.py then fails.
+Nothing here touches the HIP path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.acoustic as ac
+import oracle.hessian as hs
+import test_oracle_pins as P
+from paper_1406_1864_amd.synthetic import tiny_24x16
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return tiny_24x16(nt=300)
+
+
+def fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def plant(monkeypatch, module, name, value):
+    """Replace `name` in its oracle module and in the package namespace."""
+    monkeypatch.setattr(module, name, value)
+    if hasattr(oracle, name):
+        monkeypatch.setattr(oracle, name, value)
+
+
+def test_wrong_stencil_weight_is_caught(monkeypatch):
+    plant(monkeypatch, ac, "C8", (ac.C8[0], ac.C8[1], -ac.C8[2], ac.C8[3], ac.C8[4]))
+    fails(P.test_laplacian_exact_on_polynomials)
+
+
+def test_missing_source_scale_is_caught(monkeypatch):
+    orig = ac._source_term
+
+    def no_h2(prop, shape, dtype, siz, six, f):          # forgets the 1/h^2 of the point source
+        return orig(prop, shape, dtype, siz, six, f) * prop.h * prop.h
+    plant(monkeypatch, ac, "_source_term", no_h2)
+    fails(P.test_hankel_analytic_green_function)
+
+
+def test_amplifying_sponge_is_caught(monkeypatch):
+    orig = ac.sponge_gamma
+    plant(monkeypatch, ac, "sponge_gamma", lambda g: -orig(g))
+    fails(P.test_sponge_absorbs)
+
+
+def test_exclusive_time_integral_is_caught(monkeypatch):
+    def exclusive(d_syn, d_obs, dt):
+        r = np.asarray(d_syn, np.float64) - np.asarray(d_obs, np.float64)
+        R = dt * (np.cumsum(r, axis=-1) - r)
+        J = 0.5 * float(np.sum(R * R))
+        return J, dt * np.cumsum(R[..., ::-1], axis=-1)[..., ::-1]
+    plant(monkeypatch, ac, "misfit_time_integral", exclusive)
+    fails(P.test_time_integral_adjoint_source_explicit_matrix)
+
+
+def test_adjoint_source_scale_is_caught(monkeypatch, tiny):
+    orig = ac.adjoint
+
+    def scaled(v, grid, shot, psi):                       # injects dt^2 q psi instead of q psi
+        return orig(v, grid, shot, np.asarray(psi) * grid.dt ** 2)
+    plant(monkeypatch, ac, "adjoint", scaled)
+    fails(P.test_dot_product_adjoint, tiny)
+
+
+def test_missing_gradient_factor_is_caught(monkeypatch, tiny):
+    orig = ac.gradient
+
+    def one_over_v3(v, grid, geom, wavelet, d_obs, kind, shots=None, return_parts=False):
+        out = orig(v, grid, geom, wavelet, d_obs, kind, shots, return_parts)
+        return (out[0], out[1] / 2.0) + tuple(out[2:])   # drops the 2 of 2/v^3
+    plant(monkeypatch, ac, "gradient", one_over_v3)
+    fails(P.test_gradient_equals_jacobian_transpose_residual, tiny, P.complex_step_jacobian(tiny, P.SAMPLE_CELLS), "int")
+
+
+def test_shifted_second_difference_is_caught(monkeypatch, tiny):
+    """Correlating lam[m] with D[m+1] instead of D[m]."""
+    def shifted(v, grid, shot, wavelet, d_obs, kind, K=None):
+        siz, six, riz, rix, nt = shot
+        N, nz, nx = grid.nsponge, grid.nz, grid.nx
+        hist = []
+        traces = ac.forward(v, grid, shot, wavelet, keep=hist)
+        J, psi = ac.misfit(traces, d_obs[..., :nt], kind, grid.dt)
+        G = np.zeros((nz, nx))
+        E = np.zeros((nz, nx))
+        sl = (slice(N, N + nz), slice(N, N + nx))
+        for m, lam in ac.adjoint(v, grid, shot, psi):
+            mm = min(m + 1, nt - 1)
+            D = (hist[mm + 1] - 2 * hist[mm] + hist[mm - 1])[sl]
+            G += lam[sl] * D
+            E += D * D / grid.dt ** 3
+        return J, G, E
+    plant(monkeypatch, ac, "shot_gradient", shifted)
+    fails(P.test_gradient_equals_jacobian_transpose_residual, tiny, P.complex_step_jacobian(tiny, P.SAMPLE_CELLS), "l2")
+
+
+def test_missing_illumination_dt_is_caught(monkeypatch, tiny):
+    orig = ac.illumination
+    plant(monkeypatch, ac, "illumination", lambda *a, **k: [E * a[1].dt for E in orig(*a, **k)])
+    fails(P.test_illumination_parseval, tiny)
+
+
+def test_swapped_aperture_ends_are_caught(monkeypatch):
+    orig = hs.aperture_factor
+
+    def swapped(grid, rec_iz, rec_ix, model="pm"):
+        return -orig(grid, rec_iz, rec_ix, model)
+    plant(monkeypatch, hs, "aperture_factor", swapped)
+    fails(P.test_aperture_factor_is_inverse_distance_integral)
+
+
+def test_swapped_offset_sides_are_caught(monkeypatch):
+    def swapped(v, E_list, A_list, hmax):
+        v = np.asarray(v, np.float64)
+        nz, nx = v.shape
+        D = np.zeros((2 * hmax + 1, nz, nx))
+        for E, A in zip(E_list, A_list):
+            for h in range(-hmax, hmax + 1):
+                lo, hi = abs(h), nx - abs(h)
+                xs = np.arange(lo, hi)
+                D[h + hmax][:, xs] += E[:, xs - h] * A[:, xs + h]   # source side at x-h
+        return D * (4.0 / v ** 6)[None]
+    plant(monkeypatch, hs, "offset_diag", swapped)
+    fails(P.test_offset_diagonal_special_cases)
+
+
+def test_extended_born_side_swap_is_caught(monkeypatch, tiny):
+    orig = hs.extended_born_columns
+
+    def swapped(v, grid, shot, wavelet, cells, kind="l2"):
+        return orig(v, grid, shot, wavelet, [(iz, ix, -h) for (iz, ix, h) in cells], kind)
+    plant(monkeypatch, hs, "extended_born_columns", swapped)
+    fails(P.test_extended_born_column_is_a_point_source_response, tiny)
