@@ -105,8 +105,12 @@ typedef struct {
     int32_t tile_rows;        /* rows of one wavefront's tile (z sweep length) */
     int32_t graph_steps;      /* time steps per captured hipGraph chunk;
                                  -1 = do not use graphs                        */
-    int32_t autotune;         /* 1 = pick unset fields by timing (cached per
-                                 grid/geometry); 0 = heuristic defaults        */
+    int32_t autotune;         /* 1 = pick unset fields by timing a few steps
+                                 of each candidate inside the call's workspace;
+                                 the choice is cached per grid, geometry and
+                                 GPU model in memory and, if the environment
+                                 variable FWI_TUNE_CACHE names a file, in that
+                                 file across processes; 0 = heuristic defaults */
     int32_t prefetch;         /* rows of loads a forward-sweep wavefront keeps
                                  in flight ahead of its z sweep: 1, 3 or 7     */
     int32_t prefetch_reverse; /* same for the fused reverse sweep: 1 or 3      */
@@ -214,6 +218,11 @@ int fwi_precondition(const fwi_grid *grid, const float *v, const float *grad,
  * that used this workspace found a non-finite, non-positive or over-CFL
  * velocity on the device (its outputs are then unspecified), else 0. */
 int fwi_status(const void *workspace, void *hip_stream);
+
+/* Forgets the autotuner's choices held in this process.  Later autotuned
+ * calls read the FWI_TUNE_CACHE file again (if set) or tune again.  Must not
+ * run concurrently with a call that is being autotuned. */
+void fwi_tune_reset(void);
 
 /* Thread-local description of the last error returned on this thread. */
 const char *fwi_last_error(void);

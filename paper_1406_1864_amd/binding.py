@@ -93,6 +93,7 @@ _SIGS = {
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_status": (c_int, [c_void_p, c_void_p]),
     "fwi_last_error": (ctypes.c_char_p, []),
+    "fwi_tune_reset": (None, []),
 }
 
 
@@ -245,6 +246,10 @@ def fwi_precondition(grid, v, grad, kind, hdiag, hmax, eps, out, workspace, ws_b
     return _check(load().fwi_precondition(ctypes.byref(g), _ptr(v), _ptr(grad), int(kind), _ptr(hdiag),
                                           int(hmax), float(eps), _ptr(out), _ptr(workspace), int(ws_bytes),
                                           _stream(stream)))
+
+
+def fwi_tune_reset() -> None:
+    load().fwi_tune_reset()
 
 
 def fwi_status(workspace, stream=None) -> int:

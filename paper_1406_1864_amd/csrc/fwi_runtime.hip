@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <map>
@@ -633,10 +635,63 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   }
   k.push_back((uint64_t)ntmax);
   k.push_back((uint64_t)nrmax);
+  // the tuned choice depends on the GPU model: key it by the device's arch name
   int dev = 0;
-  hipGetDevice(&dev);
-  k.push_back((uint64_t)dev);
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    Hasher a;
+    a.bytes(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+    a.pod(prop.multiProcessorCount);
+    k.push_back(a.h);
+  }
   return k;
+}
+
+// Tuned choices persist across processes in a plain text file named by the
+// environment variable FWI_TUNE_CACHE: one line per key,
+//   "<key words in hex> : S TZ graph_steps prefetch prefetch_reverse".
+std::string key_text(const std::vector<uint64_t>& k) {
+  std::string out;
+  char buf[24];
+  for (uint64_t w : k) {
+    snprintf(buf, sizeof(buf), "%016llx ", (unsigned long long)w);
+    out += buf;
+  }
+  return out;
+}
+
+bool cache_lookup(const std::vector<uint64_t>& k, ExecChoice& c) {
+  const char* path = getenv("FWI_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  const std::string want = key_text(k);
+  char line[1024];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    const char* colon = strchr(line, ':');
+    if (!colon) continue;
+    if (std::string(line, colon - line) != want) continue;
+    ExecChoice t{};
+    if (sscanf(colon + 1, "%d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev) == 5 &&
+        t.S > 0 && t.TZ >= 8 && t.TZ <= 4096 && (t.graph_steps == -1 || (t.graph_steps > 0 && t.graph_steps <= 1024)) &&
+        (t.pf_fwd == 1 || t.pf_fwd == 3 || t.pf_fwd == 7) &&
+        (t.pf_rev == 1 || t.pf_rev == 3)) {
+      c = t;  // last matching line wins
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const std::vector<uint64_t>& k, const ExecChoice& c) {
+  const char* path = getenv("FWI_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s: %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev);
+  fclose(f);
 }
 
 // Returns the plan for a call; with autotuning requested and no cached
@@ -666,13 +721,18 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   if (tune) {
     const auto tk = tune_key(g, geo, ex, what);
     auto it = g_tuned.find(tk);
+    ExecChoice t = c;
     if (it != g_tuned.end()) {
       c = it->second;
+    } else if (cache_lookup(tk, t) && t.S <= c.S) {
+      g_tuned[tk] = t;
+      c = t;
     } else {
-      ExecChoice t = c;
+      t = c;
       int rc = autotune(g, geo, ex, what, ikey, ws, ws_bytes, v, wavelet, wstride, s, t);
       if (rc) return rc;
       g_tuned[tk] = t;
+      cache_store(tk, t);
       c = t;
     }
   }
@@ -730,6 +790,11 @@ extern "C" {
 
 const char* fwi_last_error(void) { return g_last_error.c_str(); }
 
+void fwi_tune_reset(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_tuned.clear();
+}
+
 int fwi_validate(const fwi_grid* grid, const fwi_geometry* geom) { return check_inputs(grid, geom); }
 
 int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, int what,
@@ -742,8 +807,14 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   ExecChoice c = base_choice(grid, geom, exec);
   if (!plain && exec && exec->autotune) {
     std::lock_guard<std::mutex> lock(g_mutex);
-    auto it = g_tuned.find(tune_key(grid, geom, exec, what));
-    if (it != g_tuned.end()) c = it->second;
+    const std::vector<uint64_t> tk = tune_key(grid, geom, exec, what);
+    auto it = g_tuned.find(tk);
+    ExecChoice t{};
+    if (it != g_tuned.end()) {
+      c = it->second;
+    } else if (cache_lookup(tk, t) && t.S <= c.S) {
+      c = t;
+    }
   }
   chosen->mode = exec ? exec->mode : FWI_EXEC_BATCHED;
   chosen->autotune = exec ? exec->autotune : 0;
