@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--plain-shots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=150, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="time steps of the oracle sample (0 = about 15 s of host work)")
     ap.add_argument("--nt", type=int, default=0,
                     help="shorten every record to NT samples (counter-collection runs; 0 = full)")
     ap.add_argument("--exec", type=str, default="",
@@ -232,11 +233,18 @@ def main():
     nrec = np.diff(geom.rec_ptr)
     rev_bytes = float(sum((nt[s] - 1) * reverse_bytes_per_shot_step(grid, int(nrec[s])) for s in range(shots)))
     rev_ms = phase[1] / args.steps
-    achieved = rev_bytes / (rev_ms * 1e-3) / 1e9
+    chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
+    # k_reverse launches per backward: shots run in batches of `shots_in_flight`
+    # (longest records first), each batch for its longest record
+    S = max(1, chosen["shots_in_flight"])
+    order = sorted(range(shots), key=lambda s: -int(nt[s]))
+    launches = sum(int(nt[order[b]]) - 1 for b in range(0, shots, S))
+    launch_us = rev_ms * 1e3 / max(launches, 1)
+    bytes_per_launch = rev_bytes / max(launches, 1)
+    achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
     fwd_K = int(np.ceil(np.sqrt(nt.max())))
     fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
                           for s in range(shots)))
-    chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
     full = (shots == full_shots and not args.nt)
     traffic = measured_traffic("k_reverse", chosen) if (args.workload == "layered" and full) else None
     nrec_mean = float(np.mean(nrec)) if shots else 0.0
@@ -265,8 +273,8 @@ def main():
                      "precondition": phase[2] / args.steps},
         "roofline": {"bound": "hbm", "kernel": "k_reverse", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": reverse_bytes_per_shot_step(grid, int(nrec_mean)) *
-                     min(shots, chosen["shots_in_flight"])},
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches,
+                     "avg_launch_us": launch_us},
         "copy_GBps": copy_gbs,
         "forward_roofline": {"achieved": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9, "unit": "GB/s",
                              "frac": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -297,7 +305,10 @@ def main():
         out["speedup_vs_plain"] = value / (ps / pt)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        Zc, Xc = w.grid.padded
+        # about 15 s: the oracle's gradient costs ~35 ns per padded cell and step on one core
+        nsteps = args.cpu_steps or int(np.clip(15.0 / (Zc * Xc * 3.5e-8), 50, int(w.geom.nt[0])))
+        out["cpu_baseline"] = cpu_baseline(w, nsteps)
     print(json.dumps(out), flush=True)
 
 
