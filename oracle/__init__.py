@@ -8,4 +8,4 @@ from .acoustic import (C8, CFL_LIMIT, Propagator, laplacian, sponge_gamma, padde
                        forward, forward_traces, misfit, misfit_l2, misfit_time_integral,
                        adjoint, source_adjoint, shot_gradient, gradient, illumination)
 from .hessian import (aperture_factor, offset_diag, shot_scaling, offset_scaling,
-                      precondition, extended_born_columns, offset_diag_exact)
+                      precondition, extended_born_columns, offset_diag_exact, extended_image)

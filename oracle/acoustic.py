@@ -231,9 +231,10 @@ def source_adjoint(v, grid, shot, d):
     return out
 
 
-def shot_gradient(v, grid, shot, wavelet, d_obs, kind, K=None):
+def shot_gradient(v, grid, shot, wavelet, d_obs, kind, K=None, visit=None):
     """J_s, G_s = sum_m lam[m] D[m] and E_s = sum_m (D[m]/dt^2)^2 dt on the
-    model grid, for one shot.
+    model grid, for one shot.  ``visit(m, lam[m], D[m])`` (model cells), if
+    given, sees every pair that enters G_s.
 
     Checkpointing (oracle's own, exact): the forward saves (u[n-1], u[n]) every
     K steps in FP64; the backward recomputes each K-step segment *forward*
@@ -268,6 +269,8 @@ def shot_gradient(v, grid, shot, wavelet, d_obs, kind, K=None):
             assert mm == m
             D = (seg[m] - 2.0 * seg[m - 1] + seg[m - 2])[interior]
             G += lam[interior] * D
+            if visit is not None:
+                visit(m, lam[interior], D)
             E += np.real(D * np.conj(D)) / grid.dt ** 3
             pending = next(lam_iter, None)
     return J, G, E

@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .acoustic import Propagator, forward
+from .acoustic import Propagator, forward, shot_gradient
 
 
 def aperture_factor(grid, rec_iz, rec_ix, model="pm"):
@@ -140,3 +140,35 @@ def offset_diag_exact(v, grid, geom, wavelet, cells, kind="l2"):
         cols = extended_born_columns(v, grid, shot, np.asarray(w, np.float64), cells, kind)
         total += np.sum(cols * cols, axis=(1, 2))
     return total
+
+
+def extended_image(v, grid, geom, wavelet, d_obs, kind, hmax, shots=None):
+    """Offset-extended image: the gradient of J with respect to the extended
+    model of eq. (5), i.e. the extended imaging condition of eq. (6) applied to
+    the adjoint-state wavefields,
+
+        I(x, h) = (2 / v(x)^3) sum_s sum_m lam_s[m](x - h) D_s[m](x + h),
+
+    for horizontal offsets h = -hmax .. hmax (the receiver-side wavefield at
+    x - h, the source side at x + h, 2/v^3 at the centre); terms with x - h or
+    x + h outside the model vanish.  The h = 0 slice is the gradient g.
+    Returns (J, I[2 hmax + 1][nz][nx])."""
+    v = np.asarray(v, np.float64)
+    nz, nx = v.shape
+    shots = range(geom.nshot) if shots is None else shots
+    acc = np.zeros((2 * hmax + 1, nz, nx))
+
+    def visit(m, lam, D):
+        for h in range(-hmax, hmax + 1):
+            lo, hi = abs(h), nx - abs(h)
+            if lo < hi:
+                acc[h + hmax][:, lo:hi] += lam[:, lo - h:hi - h] * D[:, lo + h:hi + h]
+
+    J = 0.0
+    for s in shots:
+        a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+        w = wavelet[s] if np.ndim(wavelet) == 2 else wavelet
+        Js, _, _ = shot_gradient(v, grid, geom.shot(s), np.asarray(w, np.float64),
+                                 np.asarray(d_obs[a:b], np.float64), kind, visit=visit)
+        J += Js
+    return J, acc * (2.0 / v ** 3)[None]

@@ -138,3 +138,25 @@ def test_extended_born_side_swap_is_caught(monkeypatch, tiny):
         return orig(v, grid, shot, wavelet, [(iz, ix, -h) for (iz, ix, h) in cells], kind)
     plant(monkeypatch, hs, "extended_born_columns", swapped)
     fails(P.test_extended_born_column_is_a_point_source_response, tiny)
+
+
+def test_extended_image_side_swap_is_caught(monkeypatch, tiny):
+    """Receiver side read at x+h and source side at x-h."""
+    def swapped(v, grid, geom, wavelet, d_obs, kind, hmax, shots=None):
+        v = np.asarray(v, np.float64)
+        nz, nx = v.shape
+        acc = np.zeros((2 * hmax + 1, nz, nx))
+
+        def visit(m, lam, D):
+            for h in range(-hmax, hmax + 1):
+                lo, hi = abs(h), nx - abs(h)
+                acc[h + hmax][:, lo:hi] += lam[:, lo + h:hi + h] * D[:, lo - h:hi - h]
+        J = 0.0
+        for s in range(geom.nshot):
+            a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+            Js, _, _ = ac.shot_gradient(v, grid, geom.shot(s), np.asarray(wavelet, np.float64),
+                                        np.asarray(d_obs[a:b], np.float64), kind, visit=visit)
+            J += Js
+        return J, acc * (2.0 / v ** 3)[None]
+    plant(monkeypatch, hs, "extended_image", swapped)
+    fails(P.test_extended_image_is_extended_born_adjoint, tiny, "l2")

@@ -353,6 +353,38 @@ def test_extended_born_column_is_a_point_source_response(tiny):
         assert np.max(np.abs(cols[k] - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+EXT_CELLS = [(8, 12, 2), (8, 12, -2), (5, 9, 1), (11, 15, -1), (2, 2, 2), (14, 21, -2), (0, 5, 1), (15, 18, 0)]
+
+
+@pytest.mark.parametrize("kind", ["l2", "int"])
+def test_extended_image_is_extended_born_adjoint(tiny, kind):
+    """Eq. (6) as the adjoint of eq. (5): I(x, h) equals the extended-Born
+    column (x, h) -- from explicit linearised runs, no adjoint code -- dotted
+    with the (time-integral weighted) residual, summed over shots; the h = 0
+    slice is the gradient, and terms reaching outside the model vanish."""
+    w = tiny
+    hmax = 2
+    v = w.v_start.astype(np.float64)
+    d_obs = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
+    d_syn = oracle.forward_traces(v, w.grid, w.geom, w.wavelet)
+    J, I = oracle.extended_image(v, w.grid, w.geom, w.wavelet, d_obs, kind, hmax)
+    ref = np.zeros(len(EXT_CELLS))
+    for s in range(w.geom.nshot):
+        a, b = w.geom.rec_ptr[s], w.geom.rec_ptr[s + 1]
+        cols = oracle.extended_born_columns(v, w.grid, w.geom.shot(s), w.wavelet.astype(np.float64), EXT_CELLS,
+                                            kind)
+        r = d_syn[a:b] - d_obs[a:b]
+        psi = w.grid.dt * np.cumsum(r, axis=-1) if kind == "int" else r
+        ref += np.einsum("krn,rn->k", cols, psi)
+    got = np.array([I[h + hmax, iz, ix] for iz, ix, h in EXT_CELLS])
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)), (got, ref)
+    Jg, g, _ = oracle.gradient(v, w.grid, w.geom, w.wavelet, d_obs, kind)
+    assert J == pytest.approx(Jg, rel=1e-14)
+    assert np.allclose(I[hmax], g, rtol=1e-12, atol=0.0)
+    for h in range(1, hmax + 1):
+        assert np.all(I[hmax + h][:, :h] == 0.0) and np.all(I[hmax - h][:, w.grid.nx - h:] == 0.0)
+
+
 def test_illumination_parseval(tiny):
     """Eq. (1) in the time domain: sum_m (D[m]/dt^2)^2 dt equals the discrete
     form of sum_omega omega^4 |u(omega)|^2, namely
