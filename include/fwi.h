@@ -127,11 +127,12 @@ enum { FWI_PRECOND_SHOT = 0,           /* P = (4/v^6) H1                       *
        FWI_PRECOND_OFFSET = 1 };       /* P = sum_h D(x, h)                    */
 /* `what` argument of fwi_workspace_bytes */
 enum { FWI_WS_FORWARD = 0, FWI_WS_GRADIENT = 1, FWI_WS_HESSIAN = 2,
-       FWI_WS_AUTOGRAD = 3, FWI_WS_PRECOND = 4 };
+       FWI_WS_AUTOGRAD = 3, FWI_WS_PRECOND = 4, FWI_WS_EXTIMAGE = 5 };
 
 /* ---------------------------------------------------------------- sizing */
 /* Bytes of device workspace needed by the matching entry point (hmax: offset
- * range of the offset diagonal, 0 if unused).  Returns 0 if the arguments fail
+ * range of the offset diagonal, 0 if unused; for FWI_WS_EXTIMAGE the offset
+ * range of the extended image, which sizes its buffers).  Returns 0 if the arguments fail
  * validation (see fwi_last_error).  FWI_WS_AUTOGRAD sizes the pair
  * fwi_misfit_forward / fwi_misfit_backward, which keeps the checkpoints of
  * every shot between the two calls. */
@@ -179,6 +180,24 @@ int fwi_gradient(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec 
                  double *J, float *grad, float *illum,
                  int hmax, int rcv_model, float *offset_diag,
                  void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Offset-extended image: eq. (6) applied to the adjoint-state wavefields,
+ * i.e. the gradient of J with respect to the extended model of eq. (5)
+ * (section 3), for horizontal subsurface offsets h = -hmax .. hmax cells:
+ *   image[h + hmax][z][x] = (2 / v(x)^3) sum_s sum_m lam_s[m](x - h) D_s[m](x + h)
+ * with lam the adjoint wavefield of fwi_gradient and D_m = u[m] - 2u[m-1] +
+ * u[m-2] of the source wavefield (receiver side at x - h, source side at
+ * x + h); a term whose x - h or x + h leaves the model is 0.  The h = 0 slice
+ * is dJ/dv.  Arguments as fwi_gradient; grad (NULL allowed) also receives
+ * dJ/dv; image is [2*hmax+1][nz][nx] float, 0 <= hmax <= 32, hmax < nx.
+ * Workspace: fwi_workspace_bytes(..., FWI_WS_EXTIMAGE, hmax); besides the
+ * gradient's buffers it holds lam and D of the model cells for graph_steps
+ * reverse steps per shot in flight (32 in plain mode). */
+int fwi_extended_image(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                       const float *v, const float *wavelet, int64_t wavelet_stride,
+                       const float *d_obs, int misfit, double *J, float *grad,
+                       int hmax, float *image,
+                       void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Hessian diagonals from the forward wavefield alone (no adjoint pass).
  *   kind FWI_HESS_EQ1:    diag [nz][nx]            = H1            (eq. (1))

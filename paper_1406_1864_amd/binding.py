@@ -39,7 +39,7 @@ MISFIT_L2, MISFIT_TIME_INTEGRAL = 0, 1
 HESS_EQ1, HESS_OFFSET = 0, 1
 RCV_PM, RCV_NONE = 0, 1
 PRECOND_SHOT, PRECOND_OFFSET = 0, 1
-WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND = 0, 1, 2, 3, 4
+WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND, WS_EXTIMAGE = 0, 1, 2, 3, 4, 5
 
 _MISFIT = {"l2": MISFIT_L2, "int": MISFIT_TIME_INTEGRAL, "time_integral": MISFIT_TIME_INTEGRAL,
            0: 0, 1: 1}
@@ -80,6 +80,9 @@ _SIGS = {
     "fwi_gradient": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
                              c_int64, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
                              c_void_p, c_size_t, c_void_p]),
+    "fwi_extended_image": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
+                                   c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p,
+                                   c_void_p, c_size_t, c_void_p]),
     "fwi_hessian_diag": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                  c_void_p, c_int64, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t,
                                  c_void_p]),
@@ -215,6 +218,15 @@ def fwi_gradient(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J
                                       _ptr(workspace), int(ws_bytes), _stream(stream)))
 
 
+def fwi_extended_image(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J, grad, hmax, image,
+                       workspace, ws_bytes, stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_extended_image(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v),
+                                            _ptr(wavelet), int(wavelet_stride), _ptr(d_obs), _MISFIT[misfit],
+                                            _ptr(J), _ptr(grad), int(hmax), _ptr(image), _ptr(workspace),
+                                            int(ws_bytes), _stream(stream)))
+
+
 def fwi_hessian_diag(grid, geom, exec_, v, wavelet, wavelet_stride, kind, hmax, rcv_model, diag, workspace,
                      ws_bytes, stream=None):
     g, G = make_grid(grid), _geo(geom)
@@ -320,6 +332,21 @@ def gradient(v, wavelet, grid, geom, d_obs, misfit="int", exec_=None, illum=True
     ws = workspace(grid, G, WS_GRADIENT, exec_, hmax or 0, device=device) if ws is None else ws
     fwi_gradient(grid, G, exec_, vd, w, ws_, dobs, misfit, J, grad, H1, hmax or 0, rcv_model, D, ws, ws.numel())
     return J, grad, H1, D
+
+
+def extended_image(v, wavelet, grid, geom, d_obs, hmax, misfit="int", exec_=None, ws=None, device="cuda"):
+    """(J, grad, image[2 hmax + 1][nz][nx]) as torch tensors on the device."""
+    torch = _torch()
+    G = _geo(geom)
+    vd = _dev(v, torch.float32, device)
+    w, ws_ = _wavelet(wavelet, grid.nt_max, device)
+    dobs = _dev(d_obs, torch.float32, device)
+    J = torch.empty((), dtype=torch.float64, device=device)
+    grad = torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=device)
+    image = torch.empty((2 * hmax + 1, grid.nz, grid.nx), dtype=torch.float32, device=device)
+    ws = workspace(grid, G, WS_EXTIMAGE, exec_, hmax, device=device) if ws is None else ws
+    fwi_extended_image(grid, G, exec_, vd, w, ws_, dobs, misfit, J, grad, hmax, image, ws, ws.numel())
+    return J, grad, image
 
 
 def hessian_diag(v, wavelet, grid, geom, kind=HESS_EQ1, hmax=0, rcv_model="pm", exec_=None, ws=None,

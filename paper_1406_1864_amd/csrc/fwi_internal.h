@@ -79,6 +79,29 @@ struct StepArgs {
   const int32_t* step_ctr;  // device step base (graph replay) or null
   int32_t step;             // step offset, or absolute step if step_ctr is null
   const int32_t* err;       // device error flag: nonzero = skip all work
+  // extended imaging (reverse sweep only): lam[m] and D[m] of the model cells
+  // are kept for the last ext_T launch steps, ring slot = step % ext_T
+  float* ext_lam;       // [slot][ext_T][model]
+  float* ext_D;         // [slot][ext_T][model]
+  int32_t ext_T;
+};
+
+// Extended imaging over one window of reverse launch steps
+// [base + step0, base + step0 + count), base = *step_ctr (or 0):
+//   I(x, h) += sum_slots sum_steps lam[m](x - h) D[m](x + h)
+struct ExtArgs {
+  Dims d;
+  int32_t S;
+  const SlotInfo* slots;
+  const ShotDesc* shots;
+  const float* lam;     // [slot][T][model]
+  const float* D;       // [slot][T][model]
+  int32_t T;
+  float* I;             // [2 hmax + 1][model]
+  int32_t hmax;
+  const int32_t* step_ctr;
+  int32_t step0, count;
+  const int32_t* err;
 };
 
 // forward-kernel feature flags
@@ -117,7 +140,11 @@ hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const S
                              int S, int use_cs, hipStream_t s);
 // prefetch: rows of loads in flight ahead of the sweep (forward 1, 3, 7; reverse 1, 3)
 hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s);
-hipError_t launch_reverse(const StepArgs& a, int prefetch, hipStream_t s);
+// ext: also keep lam[m] and D[m] for extended imaging (StepArgs::ext_*)
+hipError_t launch_reverse(const StepArgs& a, int prefetch, bool ext, hipStream_t s);
+hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
+hipError_t launch_ext_out(const Dims& d, const float* Iacc, int hmax, const float* v, float* image,
+                          const int32_t* err, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);
 hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s);
 hipError_t launch_misfit(const MisfitArgs& a, int S, int max_nrec, hipStream_t s);

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
 //   g += lam[m] D[m],  E += D[m]^2,  D[m] = w (L u[m-1] + f[m-1] e_src)
 // Same register sweep and prefetch as the forward, for two fields.
 // -------------------------------------------------------------------------
-template <int PF>
+template <int PF, bool EXT>
 __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   constexpr int W = 9 + PF;
   constexpr int R = PF + 1;
@@ -359,6 +359,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const float* strip = (m >= 3) ? a.strip + (int64_t)si.cs * a.strip_stride + (int64_t)(m - 2) * d.ring
                                 : nullptr;
   const bool first = (m == sd.nt - 1);
+  const int ext_slot = EXT ? step_of(a) % a.ext_T : 0;
   float* G = a.g + (int64_t)slot * d.model;
   float* E = a.E + (int64_t)slot * d.model;
 
@@ -459,6 +460,11 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
           u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - p0[q]);
           G[mi] = fmaf(lout, D, pg[q]);
           E[mi] = fmaf(D, D, pe[q]);
+          if (EXT) {
+            const int64_t xo = ((int64_t)slot * a.ext_T + ext_slot) * d.model + mi;
+            a.ext_lam[xo] = lout;
+            a.ext_D[xo] = D;
+          }
         } else {
           const int ri = strip_index(row, col);
           if (ri >= 0) u_m[idx] = strip ? strip[ri] : 0.0f;
@@ -466,6 +472,72 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
       }
     }
   }
+}
+
+// -------------------------------------------------------------------------
+// offset-extended imaging condition over a window of reverse steps:
+//   I(x, h) += sum_slots sum_m lam[m](x - h) D[m](x + h),  |h| <= hmax <= HM
+// One wavefront owns 64 model columns of one model row and keeps the 2HM+1
+// offset sums in registers over all slots and steps of the window; each
+// step's lam and D rows (with HM columns on each side, zero outside the
+// model) are staged in the wavefront's LDS rows, and the sums are added to I
+// once per window.
+// -------------------------------------------------------------------------
+template <int HM>
+__global__ __launch_bounds__(256) void k_ext_image(ExtArgs a) {
+  constexpr int L = kWave + 2 * HM;
+  __shared__ float shL_all[kWavesPerBlock][L];
+  __shared__ float shD_all[kWavesPerBlock][L];
+  const Dims& d = a.d;
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  const int XTm = (d.nx + kWave - 1) / kWave;
+  const int wave = blockIdx.x * kWavesPerBlock + wv;
+  if (wave >= d.nz * XTm || *a.err) return;
+  const int iz = wave / XTm, x0 = (wave % XTm) * kWave;
+  const int x = x0 + lane;
+  float* shL = shL_all[wv];
+  float* shD = shD_all[wv];
+  const int H = a.hmax;
+  const int j0 = (a.step_ctr ? *a.step_ctr : 0) + a.step0;
+  float acc[2 * HM + 1];
+#pragma unroll
+  for (int h = 0; h < 2 * HM + 1; ++h) acc[h] = 0.0f;
+  for (int s = 0; s < a.S; ++s) {
+    const SlotInfo si = a.slots[s];
+    if (si.shot < 0) continue;
+    const int nt = a.shots[si.shot].nt;
+    for (int k = 0; k < a.count; ++k) {
+      const int j = j0 + k;
+      if (nt - 1 - j < 1) break;  // this slot's shot is done from here on
+      const int64_t row = ((int64_t)s * a.T + j % a.T) * d.model + (int64_t)iz * d.nx;
+      for (int c = lane; c < L; c += kWave) {
+        const int xx = x0 - HM + c;
+        const bool in = xx >= 0 && xx < d.nx;
+        shL[c] = in ? a.lam[row + xx] : 0.0f;
+        shD[c] = in ? a.D[row + xx] : 0.0f;
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int h = -HM; h <= HM; ++h)
+        if (h >= -H && h <= H) acc[h + HM] = fmaf(shL[lane + HM - h], shD[lane + HM + h], acc[h + HM]);
+      wave_lds_fence();
+    }
+  }
+  if (x >= d.nx) return;
+  const int64_t cell = (int64_t)iz * d.nx + x;
+#pragma unroll
+  for (int h = -HM; h <= HM; ++h)
+    if (h >= -H && h <= H) a.I[(int64_t)(h + H) * d.model + cell] += acc[h + HM];
+}
+
+// image(x, h) = (2 / v(x)^3) Iacc(x, h)
+__global__ void k_ext_out(Dims d, const float* Iacc, int nh, const float* v, float* image, const int32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.model * nh) return;
+  const int64_t cell = i % d.model;
+  const double vv = v[cell];
+  image[i] = (*err) ? NAN : (float)(2.0 / (vv * vv * vv) * (double)Iacc[i]);
 }
 
 // -------------------------------------------------------------------------
@@ -731,13 +803,35 @@ hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_
   }
 }
 
-hipError_t launch_reverse(const StepArgs& a, int prefetch, hipStream_t s) {
+hipError_t launch_reverse(const StepArgs& a, int prefetch, bool ext, hipStream_t s) {
   const dim3 grid(step_blocks(a.d, a.S)), block(256);
-  switch (prefetch) {
-    case 1: hipLaunchKernelGGL(k_reverse<1>, grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_reverse<3>, grid, block, 0, s, a); break;
+  if (ext && (!a.ext_lam || !a.ext_D || a.ext_T < 1)) return hipErrorInvalidValue;
+  switch (prefetch * 2 + (ext ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_reverse<1, false>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_reverse<1, true>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_reverse<3, false>), grid, block, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_reverse<3, true>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s) {
+  const int XTm = (a.d.nx + kWave - 1) / kWave;
+  const dim3 grid(blocks_for((int64_t)a.d.nz * XTm, kWavesPerBlock)), block(256);
+  if (a.hmax < 0 || a.T < 1 || a.count < 1) return hipErrorInvalidValue;
+  if (a.hmax <= 4) hipLaunchKernelGGL(k_ext_image<4>, grid, block, 0, s, a);
+  else if (a.hmax <= 8) hipLaunchKernelGGL(k_ext_image<8>, grid, block, 0, s, a);
+  else if (a.hmax <= 16) hipLaunchKernelGGL(k_ext_image<16>, grid, block, 0, s, a);
+  else if (a.hmax <= 32) hipLaunchKernelGGL(k_ext_image<32>, grid, block, 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_ext_out(const Dims& d, const float* Iacc, int hmax, const float* v, float* image,
+                          const int32_t* err, hipStream_t s) {
+  const int nh = 2 * hmax + 1;
+  hipLaunchKernelGGL(k_ext_out, dim3(blocks_for(d.model * nh, 256)), dim3(256), 0, s, d, Iacc, nh, v, image, err);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ enum Phase { kPhaseFwd = 0, kPhaseRev = 1 };
 
 struct Layout {
   size_t hdr, shots, slots, rdir, rrows, rmaps, trace_shot;
-  size_t w, traces, jpart, u, lam, g, E, snap, strip, total;
+  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, total;
 };
 
 // device header at the start of every workspace
@@ -131,6 +131,7 @@ struct Plan {
   int S = 1, nbatch = 0, ncs = 0;
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
   int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
+  int ext_h = -1, ext_T = 0;   // extended imaging: offset bound (-1: off), ring of reverse steps
   double sp_a = 0.0;
   double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -213,9 +214,10 @@ void build_dims(Plan& p, const fwi_grid* g, int TZ) {
   d.model = (int64_t)d.nz * d.nx;
 }
 
-// what: FWI_WS_FORWARD / GRADIENT / HESSIAN / AUTOGRAD
+// what: FWI_WS_FORWARD / GRADIENT / HESSIAN / AUTOGRAD / EXTIMAGE; ext_h: offset
+// bound of the extended image (EXTIMAGE only; -1 leaves its buffers out)
 std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, const ExecChoice& ex,
-                                 int plain, int what, uint64_t key) {
+                                 int plain, int what, uint64_t key, int ext_h = -1) {
   auto p = std::make_shared<Plan>();
   p->key = key;
   p->what = what;
@@ -299,8 +301,11 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->ncs = p->split ? std::max(ns, 1) : p->S;
 
   // workspace layout
-  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD);
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE);
   const bool hess = (what == FWI_WS_HESSIAN);
+  const bool ext = (what == FWI_WS_EXTIMAGE && ext_h >= 0);
+  p->ext_h = ext ? ext_h : -1;
+  p->ext_T = ext ? (p->graph_steps > 0 ? p->graph_steps : 32) : 0;
   Layout& L = p->L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -326,6 +331,9 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->strip_stride = grad ? (int64_t)g->nt_max * d.ring : 0;
   L.snap = grad ? take(sizeof(float) * p->snap_stride * p->ncs) : o;
   L.strip = grad ? take(sizeof(float) * p->strip_stride * p->ncs) : o;
+  L.xlam = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
+  L.xD = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
+  L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1)) : o;
   L.total = o;
   return p;
 }
@@ -360,7 +368,28 @@ StepArgs step_args(const Plan& p, void* ws, int batch, const float* wavelet, int
   a.step_ctr = nullptr;
   a.step = 0;
   a.err = &at<Header>(ws, p.L.hdr)->err;
+  a.ext_lam = p.ext_h >= 0 ? at<float>(ws, p.L.xlam) : nullptr;
+  a.ext_D = p.ext_h >= 0 ? at<float>(ws, p.L.xD) : nullptr;
+  a.ext_T = p.ext_T;
   return a;
+}
+
+ExtArgs ext_args(const Plan& p, void* ws, int batch) {
+  ExtArgs e{};
+  e.d = p.d;
+  e.S = p.S;
+  e.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
+  e.shots = at<ShotDesc>(ws, p.L.shots);
+  e.lam = at<float>(ws, p.L.xlam);
+  e.D = at<float>(ws, p.L.xD);
+  e.T = p.ext_T;
+  e.I = at<float>(ws, p.L.xI);
+  e.hmax = p.ext_h;
+  e.step_ctr = nullptr;
+  e.step0 = 0;
+  e.count = 0;
+  e.err = &at<Header>(ws, p.L.hdr)->err;
+  return e;
 }
 
 hipError_t get_capture_stream(hipStream_t* out) {
@@ -379,22 +408,33 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
               int64_t wstride, hipStream_t stream) {
   if (nsteps <= 0) return FWI_OK;
   StepArgs a = step_args(p, ws, batch, wavelet, wstride);
+  // reverse sweeps of an extended-image plan keep lam and D of the last ext_T
+  // steps and fold them into the image after every ext_T steps
+  const bool ext = phase == kPhaseRev && p.ext_h >= 0;
+  ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
-    return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s) : launch_reverse(args, p.pf_rev, s);
+    return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
+                              : launch_reverse(args, p.pf_rev, ext, s);
   };
   const int T = p.graph_steps;
   if (T <= 0) {
     for (int k = 0; k < nsteps; ++k) {
       a.step = k;
       HIP_TRY(launch(a, stream));
+      if (ext && ((k + 1) % p.ext_T == 0 || k == nsteps - 1)) {
+        e.step0 = k - k % p.ext_T;
+        e.count = k % p.ext_T + 1;
+        HIP_TRY(launch_ext_image(e, stream));
+      }
     }
     return FWI_OK;
   }
+  if (ext && p.ext_T != T) return fail(FWI_ERR_STATE, "extended-image ring differs from the graph chunk");
   int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
   const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
                                       (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
                                       (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
-                                      (uint64_t)wstride};
+                                      (uint64_t)wstride, (uint64_t)ext};
   hipGraphExec_t exec = nullptr;
   auto it = p.graphs.find(gkey);
   if (it != p.graphs.end()) {
@@ -408,6 +448,13 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
     for (int k = 0; k < T && le == hipSuccess; ++k) {
       a.step = k;
       le = launch(a, cs);
+    }
+    if (ext && le == hipSuccess) {
+      ExtArgs ec = e;
+      ec.step_ctr = ctr;
+      ec.step0 = 0;
+      ec.count = T;
+      le = launch_ext_image(ec, cs);
     }
     if (le == hipSuccess) le = launch_advance(ctr, T, cs);
     hipGraph_t graph = nullptr;
@@ -433,6 +480,11 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   for (int k = full * T; k < nsteps; ++k) {
     a.step = k;
     HIP_TRY(launch(a, stream));
+  }
+  if (ext && nsteps > full * T) {
+    e.step0 = full * T;
+    e.count = nsteps - full * T;
+    HIP_TRY(launch_ext_image(e, stream));
   }
   return FWI_OK;
 }
@@ -566,7 +618,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   else PFs = {1, 3, 7};
   if (ex && ex->prefetch_reverse > 0) RFs = {ex->prefetch_reverse};
   else RFs = {1, 3};
-  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD);
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
   const int nsteps = 16;
   // best of two timings of `nsteps` launches, to keep the choice stable
@@ -633,6 +685,8 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   Hasher h;
   h.pod(*g);
   h.pod(geo->nshot);
+  // an extended-image call runs the gradient's sweeps: tune them once for both
+  if (what == FWI_WS_EXTIMAGE) what = FWI_WS_GRADIENT;
   std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
                              (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0),
                              (uint64_t)(ex ? ex->prefetch_reverse : 0)};
@@ -707,7 +761,7 @@ void cache_store(const std::vector<uint64_t>& k, const ExecChoice& c) {
 // untuned maximum, which fwi_workspace_bytes reports).
 int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, void* ws,
              size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride, hipStream_t s,
-             std::shared_ptr<Plan>& out, bool sizing_only) {
+             std::shared_ptr<Plan>& out, bool sizing_only, int ext_h = -1) {
   const int plain = ex && ex->mode == FWI_EXEC_PLAIN;
   if (ex && ex->mode != FWI_EXEC_PLAIN && ex->mode != FWI_EXEC_BATCHED) return fail(FWI_ERR_ARG, "bad exec mode");
   if (ex && (ex->shots_in_flight < 0 || ex->tile_rows < 0 || ex->graph_steps < -1))
@@ -753,6 +807,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.graph_steps);
   h.pod(c.pf_fwd);
   h.pod(c.pf_rev);
+  h.pod(ext_h);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
     if ((*it)->key == key) {
@@ -761,7 +816,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       return FWI_OK;
     }
   }
-  out = build_plan(g, geo, c, plain, what, key);
+  out = build_plan(g, geo, c, plain, what, key, ext_h);
   out->ikey = ikey;
   if (!sizing_only) {
     g_plans.push_front(out);
@@ -810,7 +865,8 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   int rc = check_inputs(grid, geom);
   if (rc) return rc;
   if (!chosen) return fail(FWI_ERR_ARG, "chosen must not be NULL");
-  if (what < FWI_WS_FORWARD || what > FWI_WS_AUTOGRAD) return fail(FWI_ERR_ARG, "bad `what`");
+  if (what < FWI_WS_FORWARD || what > FWI_WS_EXTIMAGE || what == FWI_WS_PRECOND)
+    return fail(FWI_ERR_ARG, "bad `what`");
   const int plain = exec && exec->mode == FWI_EXEC_PLAIN;
   ExecChoice c = base_choice(grid, geom, exec);
   if (!plain && exec && exec->autotune) {
@@ -838,13 +894,18 @@ size_t fwi_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const
                            int hmax) {
   if (what == FWI_WS_PRECOND) return sizeof(Header);
   if (check_inputs(grid, geom)) return 0;
-  if (what < FWI_WS_FORWARD || what > FWI_WS_AUTOGRAD) {
+  if (what < FWI_WS_FORWARD || what > FWI_WS_EXTIMAGE) {
     fail(FWI_ERR_ARG, "bad `what`");
     return 0;
   }
-  (void)hmax;
+  if (what == FWI_WS_EXTIMAGE && (hmax < 0 || hmax > 32 || hmax >= grid->nx)) {
+    fail(FWI_ERR_ARG, "image hmax must be in [0, 32] and < nx");
+    return 0;
+  }
   std::shared_ptr<Plan> p;
-  if (get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, nullptr, p, true)) return 0;
+  if (get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, nullptr, p, true,
+               what == FWI_WS_EXTIMAGE ? hmax : -1))
+    return 0;
   return p->L.total;
 }
 
@@ -878,22 +939,28 @@ int fwi_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* 
 static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
                          const float* wavelet, int64_t wstride, const float* d_obs, int misfit, double* J,
                          const double* grad_scale, float* grad, float* illum, int hmax, int rcv_model,
-                         float* offset_diag, void* ws, size_t ws_bytes, hipStream_t s, int part) {
-  // part: 0 = whole gradient, 1 = forward half (split), 2 = backward half (split)
+                         float* offset_diag, void* ws, size_t ws_bytes, hipStream_t s, int part,
+                         float* image = nullptr, int ext_h = -1) {
+  // part: 0 = whole gradient, 1 = forward half (split), 2 = backward half (split);
+  // image != null (part 0 only): also the offset-extended image for |h| <= ext_h
   int rc = common_checks(grid, geom, v, wavelet, wstride, ws);
   if (rc) return rc;
   if ((rc = check_outputs_hess(hmax, rcv_model, offset_diag, grid))) return rc;
-  const int what = part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD;
+  const bool ext = image != nullptr;
+  if (ext && (part != 0 || ext_h < 0 || ext_h > 32 || ext_h >= grid->nx))
+    return fail(FWI_ERR_ARG, "image hmax must be in [0, 32] and < nx");
+  if (!ext) ext_h = -1;
+  const int what = ext ? FWI_WS_EXTIMAGE : (part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD);
   if (part != 2) {
     if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL) return fail(FWI_ERR_ARG, "bad misfit");
     if (!J) return fail(FWI_ERR_ARG, "J must not be NULL");
     if (!d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "d_obs must not be NULL");
   }
-  if (part != 1 && !grad) return fail(FWI_ERR_ARG, "grad must not be NULL");
+  if (part != 1 && !grad && !ext) return fail(FWI_ERR_ARG, "grad must not be NULL");
   std::shared_ptr<Plan> p;
   {
     std::shared_ptr<Plan> sz;
-    if ((rc = get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, s, sz, true, ext_h))) return rc;
     if ((rc = ws_check(*sz, ws_bytes))) return rc;
   }
   if (part == 2) {
@@ -908,7 +975,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
       }
     if (!p) return fail(FWI_ERR_STATE, "fwi_misfit_backward without a matching fwi_misfit_forward");
   } else {
-    if ((rc = get_plan(grid, geom, exec, what, ws, ws_bytes, v, wavelet, wstride, s, p, false))) return rc;
+    if ((rc = get_plan(grid, geom, exec, what, ws, ws_bytes, v, wavelet, wstride, s, p, false, ext_h))) return rc;
   }
   if ((rc = ws_check(*p, ws_bytes))) return rc;
   const Plan& cp = *p;
@@ -925,6 +992,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
     HIP_TRY(launch_fill(at<float>(ws, cp.L.g), model_bytes * cp.S, s));
     if (illum) HIP_TRY(launch_fill(illum, model_bytes, s));
     if (offset_diag) HIP_TRY(launch_fill(offset_diag, model_bytes * (2 * hmax + 1), s));
+    if (ext) HIP_TRY(launch_fill(at<float>(ws, cp.L.xI), model_bytes * (2 * ext_h + 1), s));
   }
   for (int b = 0; b < cp.nbatch; ++b) {
     if (part != 2) {
@@ -949,9 +1017,10 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
       HIP_TRY(launch_fill(J, sizeof(double), s));
     }
   }
-  if (part != 1) {
+  if (part != 1 && grad) {
     HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.S, v, grad_scale, grad, &hd->err, s));
   }
+  if (ext) HIP_TRY(launch_ext_out(cp.d, at<float>(ws, cp.L.xI), ext_h, v, image, &hd->err, s));
   if (part == 1) {
     std::lock_guard<std::mutex> lock(g_mutex);
     p->fwd_ws = ws;
@@ -967,6 +1036,14 @@ int fwi_gradient(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec*
                  size_t ws_bytes, void* hip_stream) {
   return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, illum,
                        hmax, rcv_model, offset_diag, workspace, ws_bytes, (hipStream_t)hip_stream, 0);
+}
+
+int fwi_extended_image(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                       const float* wavelet, int64_t wavelet_stride, const float* d_obs, int misfit, double* J,
+                       float* grad, int hmax, float* image, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!image) return fail(FWI_ERR_ARG, "image must not be NULL");
+  return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, nullptr, 0,
+                       FWI_RCV_PM, nullptr, workspace, ws_bytes, (hipStream_t)hip_stream, 0, image, hmax);
 }
 
 int fwi_misfit_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,

@@ -116,3 +116,29 @@ def test_entry_points_reject_before_launch(lib):
     with pytest.raises(B.FwiError) as e:
         B.fwi_precondition(g, fake, fake, 5, fake, 0, 0.01, fake, fake, 256, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
+
+
+def test_extended_image_sizing_and_rejects(lib):
+    """The extended image's workspace adds its lam/D rings and offset sums to
+    the gradient's; out-of-range offsets and a missing output are rejected
+    before any HIP call."""
+    g, geo = _tiny()
+    grad = B.fwi_workspace_bytes(g, geo, None, B.WS_GRADIENT)
+    e4 = B.fwi_workspace_bytes(g, geo, None, B.WS_EXTIMAGE, 4)
+    e8 = B.fwi_workspace_bytes(g, geo, None, B.WS_EXTIMAGE, 8)
+    assert grad < e4 < e8
+    assert B.fwi_workspace_bytes(g, geo, None, B.WS_EXTIMAGE, 33) == 0
+    assert B.fwi_workspace_bytes(g, geo, None, B.WS_EXTIMAGE, -1) == 0
+    assert B.fwi_workspace_bytes(g, geo, None, B.WS_EXTIMAGE, 24) == 0   # hmax must be < nx
+    q = B.fwi_exec_query(g, geo, None, B.WS_EXTIMAGE)
+    assert q["graph_steps"] > 0
+    fake = 0x1000
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "int", fake, None, 4, None, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "int", fake, None, 40, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "int", fake, None, 4, fake, fake, 16, stream=0)
+    assert e.value.code == B.FWI_ERR_WORKSPACE
