@@ -52,6 +52,8 @@ def parse():
                     help="time steps of the oracle sample (0 = about 15 s of host work)")
     ap.add_argument("--nt", type=int, default=0,
                     help="shorten every record to NT samples (counter-collection runs; 0 = full)")
+    ap.add_argument("--ext", type=int, default=-1,
+                    help="also time the offset-extended image for |h| <= EXT against the plain gradient call")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
                          "S,TZ,graph_steps,prefetch,prefetch_reverse")
@@ -126,11 +128,40 @@ def cpu_baseline(w, nsteps):
                       f"(FP64 NumPy, single thread), extrapolated linearly to the full record"}
 
 
+def time_extended_image(args, grid, geom, w, d_obs, ex, dev):
+    """fwi_extended_image against fwi_gradient on the same workload and launch
+    configuration: calls per second and the cost of the extra offset sums."""
+    import torch
+    from paper_1406_1864_amd import binding as B
+    H = args.ext
+    ws_g = B.workspace(grid, geom, B.WS_GRADIENT, ex, device=dev)
+    ws_e = B.workspace(grid, geom, B.WS_EXTIMAGE, ex, H, device=dev)
+    res = {}
+    for name, fn in (("gradient", lambda: B.gradient(w.v_start, w.wavelet, grid, geom, d_obs, "int", ex,
+                                                      illum=False, ws=ws_g, device=dev)),
+                     ("extended_image", lambda: B.extended_image(w.v_start, w.wavelet, grid, geom, d_obs, H, "int",
+                                                                 ex, ws=ws_e, device=dev))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    nt = geom.nt.astype(np.int64)
+    # extra traffic per model cell-step: lam and D written to and read back from
+    # the window ring (16 B); the offset sums add (2H+1) x 8 B per cell per window
+    return {"hmax": H, "value": geom.nshot / res["extended_image"], "unit": "shot-images/s",
+            "ms_per_call": 1e3 * res["extended_image"], "gradient_ms_per_call": 1e3 * res["gradient"],
+            "overhead_vs_gradient": res["extended_image"] / res["gradient"] - 1.0,
+            "model_cell_steps_per_s": float(np.sum(nt - 1)) * grid.nz * grid.nx / res["extended_image"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by shots and "
-              "multi-GPU runs are not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path would shard by shots "
+              "(a subset per GPU and one all-reduce of g, H1, D and J), which is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1406_1864_amd import binding as B
@@ -303,6 +334,9 @@ def main():
         out["plain"] = {"value": ps / pt, "unit": "shot-gradients/s", "shots": ps,
                         "path": "one shot per launch, one launch per time step, no graph"}
         out["speedup_vs_plain"] = value / (ps / pt)
+
+    if args.ext >= 0:
+        out["extended_image"] = time_extended_image(args, grid, geom, w, d_obs, ex, dev)
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded
