@@ -234,20 +234,31 @@ def source_adjoint(v, grid, shot, d):
 def shot_gradient(v, grid, shot, wavelet, d_obs, kind, K=None, visit=None):
     """J_s, G_s = sum_m lam[m] D[m] and E_s = sum_m (D[m]/dt^2)^2 dt on the
     model grid, for one shot.  ``visit(m, lam[m], D[m])`` (model cells), if
-    given, sees every pair that enters G_s.
-
-    Checkpointing (oracle's own, exact): the forward saves (u[n-1], u[n]) every
-    K steps in FP64; the backward recomputes each K-step segment *forward*
-    from its saved state and then runs the adjoint through it."""
+    given, sees every pair that enters G_s."""
     siz, six, riz, rix, nt = shot
     wavelet = np.asarray(wavelet, np.float64)
-    N, nz, nx = grid.nsponge, grid.nz, grid.nx
     K = K or max(1, int(math.ceil(math.sqrt(nt))))
     traces, saves = forward(v, grid, shot, wavelet, save_every=K)
     J, psi = misfit(traces, d_obs[..., :nt], kind, grid.dt)
+    G, E = imaging(v, grid, shot, wavelet, psi, saves, K, visit)
+    return J, G, E
+
+
+def imaging(v, grid, shot, wavelet, psi, saves, K, visit=None):
+    """G_s = sum_m lam[m] D[m] and E_s = sum_m (D[m]/dt^2)^2 dt on the model
+    grid, with lam back-propagated from the adjoint source ``psi`` [nrec, nt]
+    and D[m] = u[m] - 2u[m-1] + u[m-2] of the source wavefield.
+
+    Checkpointing (oracle's own, exact): ``saves`` holds (u[n-1], u[n]) every
+    K steps in FP64 (``forward(..., save_every=K)``); each K-step segment is
+    recomputed *forward* from its saved state and the adjoint runs through
+    it."""
+    siz, six, riz, rix, nt = shot
+    wavelet = np.asarray(wavelet, np.float64)
+    N, nz, nx = grid.nsponge, grid.nz, grid.nx
     prop = Propagator(v, grid)
     sz, sx = prop.cell(siz, six)
-    G = np.zeros(prop.q.shape[:-2] + (nz, nx), np.result_type(prop.q.dtype, np.float64))
+    G = np.zeros(prop.q.shape[:-2] + (nz, nx), np.result_type(prop.q.dtype, np.asarray(psi).dtype, np.float64))
     E = np.zeros((nz, nx), np.float64)
     interior = (Ellipsis, slice(N, N + nz), slice(N, N + nx))
 
@@ -273,7 +284,7 @@ def shot_gradient(v, grid, shot, wavelet, d_obs, kind, K=None, visit=None):
                 visit(m, lam[interior], D)
             E += np.real(D * np.conj(D)) / grid.dt ** 3
             pending = next(lam_iter, None)
-    return J, G, E
+    return G, E
 
 
 def gradient(v, grid, geom, wavelet, d_obs, kind, shots=None, return_parts=False):

@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .acoustic import Propagator, forward, shot_gradient
+from .acoustic import Propagator, _source_term, forward, imaging, misfit, shot_gradient
 
 
 def aperture_factor(grid, rec_iz, rec_ix, model="pm"):
@@ -172,3 +172,69 @@ def extended_image(v, grid, geom, wavelet, d_obs, kind, hmax, shots=None):
                                  np.asarray(d_obs[a:b], np.float64), kind, visit=visit)
         J += Js
     return J, acc * (2.0 / v ** 3)[None]
+
+
+def born_shot(v, grid, shot, wavelet, dv):
+    """Linearised traces dd = J dv of one shot: the Born operator of eq. (4)
+    in the discrete scheme.  The perturbation wavefield obeys the scheme
+    linearised in v at the model cells (padding frozen), started from zero;
+    in the update that yields du[m] it receives dt^2 dq (L u[m-1] + s[m-1])
+    with dq = 2 v dv, which inside the model equals (2 dv / v) D[m],
+    D[m] = u[m] - 2u[m-1] + u[m-2].  Returns [nrec, nt]."""
+    siz, six, riz, rix, nt = shot
+    wavelet = np.asarray(wavelet, np.float64)
+    v = np.asarray(v, np.float64)
+    N, nz, nx = grid.nsponge, grid.nz, grid.nx
+    prop = Propagator(v, grid)
+    sz, sx = prop.cell(siz, six)
+    rz, rx = prop.cell(np.asarray(riz), np.asarray(rix))
+    # step() adds dt^2 q extra: extra = (2 dv / v^3) D / dt^2 gives (2 dv / v) D
+    coef = np.zeros(prop.q.shape)
+    coef[N:N + nz, N:N + nx] = 2.0 * np.asarray(dv, np.float64) / v ** 3 / grid.dt ** 2
+    u_prev = np.zeros(prop.q.shape)
+    u = np.zeros(prop.q.shape)
+    du_prev = np.zeros(prop.q.shape)
+    du = np.zeros(prop.q.shape)
+    out = np.zeros((len(riz), nt))
+    for n in range(nt - 1):
+        un = prop.step(u, u_prev, _source_term(prop, prop.q.shape, np.float64, sz, sx, wavelet[n]))
+        dun = prop.step(du, du_prev, coef * (un - 2.0 * u + u_prev))
+        u_prev, u = u, un
+        du_prev, du = du, dun
+        out[:, n + 1] = du[rz, rx]
+    return out
+
+
+def born(v, grid, geom, wavelet, dv, shots=None):
+    """Born data J dv [ntrace][nt_max] (zero past each shot's record)."""
+    shots = range(geom.nshot) if shots is None else shots
+    out = np.zeros((geom.ntrace, grid.nt_max))
+    for s in shots:
+        a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+        w = wavelet[s] if np.ndim(wavelet) == 2 else wavelet
+        shot = geom.shot(s)
+        out[a:b, :shot[4]] = born_shot(v, grid, shot, w, dv)
+    return out
+
+
+def gn_hvp(v, grid, geom, wavelet, dv, kind, shots=None):
+    """Gauss-Newton Hessian times a model perturbation (section 1, H = J^T J
+    with the data weighting of the misfit): returns
+    (1/2 |W J dv|^2, J^T W^T W J dv) on the model cells, W = I (conventional)
+    or the time integral of eq. (2).  The product is the gradient machinery
+    with the Born data as the residual."""
+    v = np.asarray(v, np.float64)
+    shots = range(geom.nshot) if shots is None else shots
+    Jb = 0.0
+    G = np.zeros_like(v)
+    for s in shots:
+        shot = geom.shot(s)
+        w = np.asarray(wavelet[s] if np.ndim(wavelet) == 2 else wavelet, np.float64)
+        dd = born_shot(v, grid, shot, w, dv)
+        Js, psi = misfit(dd, np.zeros_like(dd), kind, grid.dt)
+        K = max(1, int(np.ceil(np.sqrt(shot[4]))))
+        _, saves = forward(v, grid, shot, w, save_every=K)
+        Gs, _ = imaging(v, grid, shot, w, psi, saves, K)
+        Jb += Js
+        G += Gs
+    return Jb, 2.0 / v ** 3 * G

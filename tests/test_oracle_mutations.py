@@ -160,3 +160,13 @@ def test_extended_image_side_swap_is_caught(monkeypatch, tiny):
         return J, acc * (2.0 / v ** 3)[None]
     plant(monkeypatch, hs, "extended_image", swapped)
     fails(P.test_extended_image_is_extended_born_adjoint, tiny, "l2")
+
+
+def test_born_missing_factor_is_caught(monkeypatch, tiny):
+    """Born source (dv / v) D instead of (2 dv / v) D."""
+    orig = hs.born_shot
+
+    def half(v, grid, shot, wavelet, dv):
+        return orig(v, grid, shot, wavelet, 0.5 * np.asarray(dv))
+    plant(monkeypatch, hs, "born_shot", half)
+    fails(P.test_born_is_the_complex_step_derivative, tiny)

@@ -353,6 +353,52 @@ def test_extended_born_column_is_a_point_source_response(tiny):
         assert np.max(np.abs(cols[k] - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+def test_born_is_the_complex_step_derivative(tiny):
+    """Eq. (4) discretised: J dv equals the complex-step derivative of the
+    traces along dv (v_pad perturbed on model cells only, padding frozen)."""
+    w = tiny
+    eps = 1e-30
+    N = w.grid.nsponge
+    rng = np.random.default_rng(7)
+    dv = rng.standard_normal((w.grid.nz, w.grid.nx)) * 20.0
+    vp = np.pad(w.v_start.astype(np.float64), N, mode="edge").astype(np.complex128)
+    vp[N:N + w.grid.nz, N:N + w.grid.nx] += 1j * eps * dv
+    got = oracle.born(w.v_start, w.grid, w.geom, w.wavelet, dv)
+    for s in range(w.geom.nshot):
+        p = oracle.Propagator(w.v_start, w.grid)
+        p.q = vp * vp
+        p.dt2q = w.grid.dt ** 2 * p.q
+        ref = _forward_with(p, w.geom.shot(s), w.wavelet.astype(np.float64)).imag / eps
+        a, b = w.geom.rec_ptr[s], w.geom.rec_ptr[s + 1]
+        assert np.max(np.abs(got[a:b] - ref)) <= 1e-12 * np.max(np.abs(ref)), s
+
+
+@pytest.mark.parametrize("kind", ["l2", "int"])
+def test_gn_hvp_equals_jacobian_products(tiny, jac, kind):
+    """H dv = J^T W^T W J dv with J the complex-step Jacobian (no adjoint
+    code) for dv supported on the sampled cells; 1/2 |W J dv|^2 alongside."""
+    w = tiny
+    rng = np.random.default_rng(11)
+    coeff = rng.standard_normal(len(SAMPLE_CELLS)) * 30.0
+    dv = np.zeros((w.grid.nz, w.grid.nx))
+    for c, (iz, ix) in zip(coeff, SAMPLE_CELLS):
+        dv[iz, ix] = c
+    Jb, Hdv = oracle.gn_hvp(w.v_start, w.grid, w.geom, w.wavelet, dv, kind)
+    nt = w.grid.nt_max
+    W = w.grid.dt * np.tril(np.ones((nt, nt))) if kind == "int" else np.eye(nt)
+    ref = np.zeros(len(SAMPLE_CELLS))
+    Jref = 0.0
+    for s in range(w.geom.nshot):
+        dd = np.einsum("krn,k->rn", jac[s], coeff)           # J_s dv
+        Wdd = dd @ W.T
+        Jref += 0.5 * np.sum(Wdd * Wdd)
+        ref += np.einsum("krn,rn->k", jac[s], Wdd @ W)
+    got = np.array([Hdv[c] for c in SAMPLE_CELLS])
+    assert Jb == pytest.approx(Jref, rel=1e-10)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)), (got, ref)
+    assert float(np.sum(dv * Hdv)) == pytest.approx(2.0 * Jb, rel=1e-10)
+
+
 EXT_CELLS = [(8, 12, 2), (8, 12, -2), (5, 9, 1), (11, 15, -1), (2, 2, 2), (14, 21, -2), (0, 5, 1), (15, 18, 0)]
 
 
