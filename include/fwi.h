@@ -127,7 +127,8 @@ enum { FWI_PRECOND_SHOT = 0,           /* P = (4/v^6) H1                       *
        FWI_PRECOND_OFFSET = 1 };       /* P = sum_h D(x, h)                    */
 /* `what` argument of fwi_workspace_bytes */
 enum { FWI_WS_FORWARD = 0, FWI_WS_GRADIENT = 1, FWI_WS_HESSIAN = 2,
-       FWI_WS_AUTOGRAD = 3, FWI_WS_PRECOND = 4, FWI_WS_EXTIMAGE = 5 };
+       FWI_WS_AUTOGRAD = 3, FWI_WS_PRECOND = 4, FWI_WS_EXTIMAGE = 5,
+       FWI_WS_BORN = 6, FWI_WS_GNHVP = 7 };
 
 /* ---------------------------------------------------------------- sizing */
 /* Bytes of device workspace needed by the matching entry point (hmax: offset
@@ -198,6 +199,31 @@ int fwi_extended_image(const fwi_grid *grid, const fwi_geometry *geom, const fwi
                        const float *d_obs, int misfit, double *J, float *grad,
                        int hmax, float *image,
                        void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Born modelling (eq. (4)): the linearisation of fwi_forward in v along dv,
+ * data = J dv.  The perturbation wavefield du obeys the scheme linearised at
+ * the model cells (the sponge padding is frozen), starts from zero and in the
+ * update that yields du[m] receives (2 dv / v) D[m], D[m] = u[m] - 2u[m-1] +
+ * u[m-2]; data[r][n] = du[n] at receiver r.
+ *   dv    [nz][nx] float, m/s
+ *   data  [rec_ptr[nshot]][nt_max] float out, zero for n >= nt[s]
+ * Workspace: fwi_workspace_bytes(..., FWI_WS_BORN, 0). */
+int fwi_born(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+             const float *v, const float *wavelet, int64_t wavelet_stride,
+             const float *dv, float *data,
+             void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Gauss-Newton Hessian-vector product (section 1, H = J^T J with the data
+ * weighting W of the misfit): hv = J^T W^T W J dv on the model cells and
+ * J = 1/2 |W J dv|^2 (device double), so that <dv, hv> = 2 J.  Runs Born
+ * modelling (as fwi_born) with the source wavefield's checkpoints, takes the
+ * Born data as the residual, and the adjoint sweep of fwi_gradient.
+ *   misfit  FWI_MISFIT_L2 (W = I) or FWI_MISFIT_TIME_INTEGRAL (eq. (2))
+ * Workspace: fwi_workspace_bytes(..., FWI_WS_GNHVP, 0). */
+int fwi_gn_hvp(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+               const float *v, const float *wavelet, int64_t wavelet_stride,
+               const float *dv, int misfit, double *J, float *hv,
+               void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Hessian diagonals from the forward wavefield alone (no adjoint pass).
  *   kind FWI_HESS_EQ1:    diag [nz][nx]            = H1            (eq. (1))

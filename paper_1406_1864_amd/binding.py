@@ -39,7 +39,7 @@ MISFIT_L2, MISFIT_TIME_INTEGRAL = 0, 1
 HESS_EQ1, HESS_OFFSET = 0, 1
 RCV_PM, RCV_NONE = 0, 1
 PRECOND_SHOT, PRECOND_OFFSET = 0, 1
-WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND, WS_EXTIMAGE = 0, 1, 2, 3, 4, 5
+WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND, WS_EXTIMAGE, WS_BORN, WS_GNHVP = range(8)
 
 _MISFIT = {"l2": MISFIT_L2, "int": MISFIT_TIME_INTEGRAL, "time_integral": MISFIT_TIME_INTEGRAL,
            0: 0, 1: 1}
@@ -83,6 +83,10 @@ _SIGS = {
     "fwi_extended_image": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                    c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p,
                                    c_void_p, c_size_t, c_void_p]),
+    "fwi_born": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
+                         c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "fwi_gn_hvp": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
+                           c_int64, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_hessian_diag": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                  c_void_p, c_int64, c_int, c_int, c_int, c_void_p, c_void_p, c_size_t,
                                  c_void_p]),
@@ -227,6 +231,20 @@ def fwi_extended_image(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, mis
                                             int(ws_bytes), _stream(stream)))
 
 
+def fwi_born(grid, geom, exec_, v, wavelet, wavelet_stride, dv, data, workspace, ws_bytes, stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_born(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v), _ptr(wavelet),
+                                  int(wavelet_stride), _ptr(dv), _ptr(data), _ptr(workspace), int(ws_bytes),
+                                  _stream(stream)))
+
+
+def fwi_gn_hvp(grid, geom, exec_, v, wavelet, wavelet_stride, dv, misfit, J, hv, workspace, ws_bytes, stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_gn_hvp(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v), _ptr(wavelet),
+                                    int(wavelet_stride), _ptr(dv), _MISFIT[misfit], _ptr(J), _ptr(hv),
+                                    _ptr(workspace), int(ws_bytes), _stream(stream)))
+
+
 def fwi_hessian_diag(grid, geom, exec_, v, wavelet, wavelet_stride, kind, hmax, rcv_model, diag, workspace,
                      ws_bytes, stream=None):
     g, G = make_grid(grid), _geo(geom)
@@ -347,6 +365,33 @@ def extended_image(v, wavelet, grid, geom, d_obs, hmax, misfit="int", exec_=None
     ws = workspace(grid, G, WS_EXTIMAGE, exec_, hmax, device=device) if ws is None else ws
     fwi_extended_image(grid, G, exec_, vd, w, ws_, dobs, misfit, J, grad, hmax, image, ws, ws.numel())
     return J, grad, image
+
+
+def born(v, wavelet, grid, geom, dv, exec_=None, ws=None, device="cuda"):
+    """Born data J dv [ntrace][nt_max] (torch float32 on the device)."""
+    torch = _torch()
+    G = _geo(geom)
+    vd = _dev(v, torch.float32, device)
+    dvd = _dev(dv, torch.float32, device)
+    w, ws_ = _wavelet(wavelet, grid.nt_max, device)
+    data = torch.empty((max(geom.ntrace, 1), grid.nt_max), dtype=torch.float32, device=device)
+    ws = workspace(grid, G, WS_BORN, exec_, device=device) if ws is None else ws
+    fwi_born(grid, G, exec_, vd, w, ws_, dvd, data, ws, ws.numel())
+    return data[:geom.ntrace]
+
+
+def gn_hvp(v, wavelet, grid, geom, dv, misfit="int", exec_=None, ws=None, device="cuda"):
+    """(1/2 |W J dv|^2, J^T W^T W J dv) as torch tensors on the device."""
+    torch = _torch()
+    G = _geo(geom)
+    vd = _dev(v, torch.float32, device)
+    dvd = _dev(dv, torch.float32, device)
+    w, ws_ = _wavelet(wavelet, grid.nt_max, device)
+    J = torch.empty((), dtype=torch.float64, device=device)
+    hv = torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=device)
+    ws = workspace(grid, G, WS_GNHVP, exec_, device=device) if ws is None else ws
+    fwi_gn_hvp(grid, G, exec_, vd, w, ws_, dvd, misfit, J, hv, ws, ws.numel())
+    return J, hv
 
 
 def hessian_diag(v, wavelet, grid, geom, kind=HESS_EQ1, hmax=0, rcv_model="pm", exec_=None, ws=None,

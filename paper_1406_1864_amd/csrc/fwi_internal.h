@@ -84,6 +84,9 @@ struct StepArgs {
   float* ext_lam;       // [slot][ext_T][model]
   float* ext_D;         // [slot][ext_T][model]
   int32_t ext_T;
+  // Born modelling (forward sweep only): the perturbation wavefield
+  float* bu;            // [cs][3][field]  du[n] at level n & 1, its increment at level 2
+  const float* bw;      // 2 dv / v on the padded grid (zero outside the model)
 };
 
 // Extended imaging over one window of reverse launch steps
@@ -105,7 +108,8 @@ struct ExtArgs {
 };
 
 // forward-kernel feature flags
-enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4 };
+// kFwdBorn: also step the Born perturbation wavefield and record it instead of u
+enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8 };
 
 struct MisfitArgs {
   const SlotInfo* slots;
@@ -136,6 +140,8 @@ struct EpiArgs {
 hipError_t launch_prep(const Dims& d, const float* v, float* w, double dt, double h, float vmax,
                        int32_t* err, hipStream_t s);
 hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s);
+// bw = 2 dv / v on the model cells of the padded grid (storage layout), 0 elsewhere
+hipError_t launch_prep_born(const Dims& d, const float* v, const float* dv, float* bw, hipStream_t s);
 hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const SlotInfo* slots,
                              int S, int use_cs, hipStream_t s);
 // prefetch: rows of loads in flight ahead of the sweep (forward 1, 3, 7; reverse 1, 3)

@@ -173,7 +173,9 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   constexpr int W = 9 + PF;  // stencil-row ring
   constexpr int R = PF + 1;  // point-wise ring; W % R == 0 keeps slots static
   static_assert(W % R == 0, "prefetch distance must make the rings commensurate");
+  constexpr bool BORN = (FLAGS & kFwdBorn) != 0;
   __shared__ float lds_all[kWavesPerBlock][kWave + 2 * kRadius];
+  __shared__ float ldsB_all[kWavesPerBlock][BORN ? kWave + 2 * kRadius : 1];
   const int lane = threadIdx.x & 63;
   const int wv = uniform(threadIdx.x >> 6);
   int slot, tile;
@@ -195,6 +197,12 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   const float* ucur = ubase + (int64_t)(n & 1) * d.field;
   float* unxt = ubase + (int64_t)((n + 1) & 1) * d.field;
   float* dinc = ubase + (int64_t)2 * d.field;
+  // Born: du with the same level layout as u
+  float* bbase = BORN ? a.bu + (int64_t)si.cs * kULevels * d.field : nullptr;
+  const float* bcur = BORN ? bbase + (int64_t)(n & 1) * d.field : nullptr;
+  float* bnxt = BORN ? bbase + (int64_t)((n + 1) & 1) * d.field : nullptr;
+  float* binc = BORN ? bbase + (int64_t)2 * d.field : nullptr;
+  float* ldsB = ldsB_all[wv];
 
   const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
   const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + n] : 0.0f;
@@ -222,9 +230,20 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   float* E = (FLAGS & kFwdIllum) ? a.E + (int64_t)slot * d.model : nullptr;
 
   float wc[W], wh[W], pd[R], pw[R];
+  float bc[BORN ? W : 1], bh[BORN ? W : 1], pbd[BORN ? R : 1], pbw[BORN ? R : 1];
   auto load_row = [&](int r, float& c, float& h) {
     if (r >= 0 && r < d.Z) {
       const float* row = ucur + (int64_t)r * d.P;
+      c = row[col.xs];
+      h = col.hok ? row[col.hcol] : 0.0f;
+    } else {
+      c = 0.0f;
+      h = 0.0f;
+    }
+  };
+  auto load_brow = [&](int r, float& c, float& h) {
+    if (r >= 0 && r < d.Z) {
+      const float* row = bcur + (int64_t)r * d.P;
       c = row[col.xs];
       h = col.hok ? row[col.hcol] : 0.0f;
     } else {
@@ -237,11 +256,22 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
     p = dinc[idx];
     w = a.w[idx];
   };
+  auto load_bpt = [&](int r, float& p, float& f) {
+    const int64_t idx = (int64_t)r * d.P + col.xs;
+    p = binc[idx];
+    f = a.bw[idx];
+  };
 #pragma unroll
-  for (int j = 0; j < 8 + PF; ++j) load_row(z0 - 4 + j, wc[j], wh[j]);
+  for (int j = 0; j < 8 + PF; ++j) {
+    load_row(z0 - 4 + j, wc[j], wh[j]);
+    if (BORN) load_brow(z0 - 4 + j, bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
+  }
 #pragma unroll
   for (int j = 0; j < PF; ++j)
-    if (z0 + j < z1) load_pt(z0 + j, pd[j], pw[j]);
+    if (z0 + j < z1) {
+      load_pt(z0 + j, pd[j], pw[j]);
+      if (BORN) load_bpt(z0 + j, pbd[j % (BORN ? R : 1)], pbw[j % (BORN ? R : 1)]);
+    }
 
   for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
@@ -251,30 +281,51 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
       if (z + PF < z1) {
         load_row(z + 4 + PF, wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
         load_pt(z + PF, pd[(r + PF) % R], pw[(r + PF) % R]);
+        if (BORN) {
+          load_brow(z + 4 + PF, bc[(r + 8 + PF) % (BORN ? W : 1)], bh[(r + 8 + PF) % (BORN ? W : 1)]);
+          load_bpt(z + PF, pbd[(r + PF) % (BORN ? R : 1)], pbw[(r + PF) % (BORN ? R : 1)]);
+        }
       }
       const float c = wc[(r + 4) % W];
       lds_put(lds, lane, c, wh[(r + 4) % W]);
+      float bcv = 0.0f;
+      if (BORN) {
+        bcv = bc[(r + 4) % (BORN ? W : 1)];
+        lds_put(ldsB, lane, bcv, bh[(r + 4) % (BORN ? W : 1)]);
+      }
       wave_lds_fence();
       float lap = laplace<W>(wc, r + 4, lds, lane);
+      float blap = 0.0f;
+      if (BORN) blap = laplace<BORN ? W : 1>(bc, r + 4, ldsB, lane);
       wave_lds_fence();
       if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lap += fsrc;
 
       const Row row = make_row(d, z);
       const float dn = pd[r % R], wv_ = pw[r % R];
-      float out = 0.0f;
+      float out = 0.0f, bout = 0.0f;
       if (col.xin) {
         const int dd = max(row.dz, col.dxs);
-        float dnew;
+        float dnew, bdnew = 0.0f;
         if (dd == 0) {
           dnew = fmaf(wv_, lap, dn);
+          // Born: d(du) = w (L du + (2 dv / v)(L u + s)), the linearised update
+          if (BORN) bdnew = fmaf(wv_, fmaf(pbw[r % (BORN ? R : 1)], lap, blap), pbd[r % (BORN ? R : 1)]);
         } else {
           const double gm = a.sp_a * (double)(dd * dd);
           dnew = (float)(((1.0 - gm) * (double)dn + (double)wv_ * (double)lap) / (1.0 + gm));
+          if (BORN)
+            bdnew = (float)(((1.0 - gm) * (double)pbd[r % (BORN ? R : 1)] + (double)wv_ * (double)blap) /
+                            (1.0 + gm));
         }
         out = c + dnew;
         const int64_t idx = (int64_t)z * d.P + col.xs;
         unxt[idx] = out;
         dinc[idx] = dnew;
+        if (BORN) {
+          bout = bcv + bdnew;
+          bnxt[idx] = bout;
+          binc[idx] = bdnew;
+        }
         const bool mcell = row.model && col.mcol;
         const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
         if ((FLAGS & kFwdIllum) && mcell) {
@@ -293,7 +344,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
       if (FLAGS & kFwdRecord) {
         if (z == rz) {
           const int tr = a.rmaps[a.rrows[rp].map + lane];
-          if (tr >= 0) a.traces[(int64_t)(n + 1) * a.ntrace + tr] = out;
+          if (tr >= 0) a.traces[(int64_t)(n + 1) * a.ntrace + tr] = BORN ? bout : out;
           ++rp;
           rz = rp < rend ? a.rrows[rp].z : INT_MAX;
         }
@@ -558,6 +609,20 @@ __global__ void k_prep(Dims d, const float* __restrict__ v, float* __restrict__ 
   w[i] = out;
 }
 
+__global__ void k_prep_born(Dims d, const float* __restrict__ v, const float* __restrict__ dv,
+                            float* __restrict__ bw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.field) return;
+  const int z = (int)(i / d.P), xs = (int)(i % d.P);
+  const int mz = z - d.N, mx = xs - d.mx0;
+  float out = 0.0f;
+  if (mz >= 0 && mz < d.nz && mx >= 0 && mx < d.nx) {
+    const int64_t m = (int64_t)mz * d.nx + mx;
+    out = 2.0f * dv[m] / v[m];
+  }
+  bw[i] = out;
+}
+
 __global__ void k_fill(uint32_t* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -586,13 +651,14 @@ __global__ void k_misfit(MisfitArgs a) {
   if (r >= sd.nrec) return;
   const int tr = sd.rec_begin + r;
   float* syn = a.traces + tr;
-  const float* obs = a.dobs + (int64_t)tr * a.nt_max;
+  // no recorded data (Gauss-Newton products): the residual is the synthetic itself
+  const float* obs = a.dobs ? a.dobs + (int64_t)tr * a.nt_max : nullptr;
   const int64_t st = a.ntrace;
   const int nt = sd.nt;
   double J = 0.0;
   if (a.kind == 0) {
     for (int t = 0; t < nt; ++t) {
-      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (obs ? (double)obs[t] : 0.0);
       J += rr * rr;
       syn[t * st] = (float)(rr * a.psi_scale);
     }
@@ -600,14 +666,14 @@ __global__ void k_misfit(MisfitArgs a) {
     // eq. (2): R[n] = dt sum_{k<=n} r[k]; psi[n] = dt sum_{k>=n} R[k] = dt (S - sum_{k<n} R[k])
     double R = 0.0, S = 0.0;
     for (int t = 0; t < nt; ++t) {
-      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (obs ? (double)obs[t] : 0.0);
       R += a.dt * rr;
       J += R * R;
       S += R;
     }
     double Rp = 0.0, Pn = 0.0;
     for (int t = 0; t < nt; ++t) {
-      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (double)obs[t];
+      const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (obs ? (double)obs[t] : 0.0);
       Rp += a.dt * rr;
       syn[t * st] = (float)(a.dt * (S - Pn) * a.psi_scale);
       Pn += Rp;
@@ -763,6 +829,11 @@ hipError_t launch_prep(const Dims& d, const float* v, float* w, double dt, doubl
   return hipGetLastError();
 }
 
+hipError_t launch_prep_born(const Dims& d, const float* v, const float* dv, float* bw, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_born, dim3(blocks_for(d.field, 256)), dim3(256), 0, s, d, v, dv, bw);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(void* p, size_t nbytes, hipStream_t s) {
   const size_t n = nbytes / 4;
   if (n == 0) return hipSuccess;
@@ -789,12 +860,19 @@ static hipError_t launch_forward_pf(const StepArgs& a, int flags, hipStream_t s)
       hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt, PF>), grid, block, 0, s, a);
       break;
     case kFwdIllum: hipLaunchKernelGGL((k_forward<kFwdIllum, PF>), grid, block, 0, s, a); break;
+    case kFwdRecord | kFwdBorn:
+      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdBorn, PF>), grid, block, 0, s, a);
+      break;
+    case kFwdRecord | kFwdCkpt | kFwdBorn:
+      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt | kFwdBorn, PF>), grid, block, 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s) {
+  if ((flags & kFwdBorn) && (!a.bu || !a.bw)) return hipErrorInvalidValue;
   switch (prefetch) {
     case 1: return launch_forward_pf<1>(a, flags, s);
     case 3: return launch_forward_pf<3>(a, flags, s);

@@ -112,7 +112,7 @@ enum Phase { kPhaseFwd = 0, kPhaseRev = 1 };
 
 struct Layout {
   size_t hdr, shots, slots, rdir, rrows, rmaps, trace_shot;
-  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, total;
+  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, bu, bw, total;
 };
 
 // device header at the start of every workspace
@@ -132,6 +132,7 @@ struct Plan {
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
   int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
   int ext_h = -1, ext_T = 0;   // extended imaging: offset bound (-1: off), ring of reverse steps
+  int born = 0;                // Born perturbation wavefield buffers present
   double sp_a = 0.0;
   double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -301,8 +302,10 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->ncs = p->split ? std::max(ns, 1) : p->S;
 
   // workspace layout
-  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE);
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
+                     what == FWI_WS_GNHVP);
   const bool hess = (what == FWI_WS_HESSIAN);
+  p->born = (what == FWI_WS_BORN || what == FWI_WS_GNHVP) ? 1 : 0;
   const bool ext = (what == FWI_WS_EXTIMAGE && ext_h >= 0);
   p->ext_h = ext ? ext_h : -1;
   p->ext_T = ext ? (p->graph_steps > 0 ? p->graph_steps : 32) : 0;
@@ -334,6 +337,8 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.xlam = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
   L.xD = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
   L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1)) : o;
+  L.bu = p->born ? take(sizeof(float) * kULevels * d.field * p->ncs) : o;
+  L.bw = p->born ? take(sizeof(float) * d.field) : o;
   L.total = o;
   return p;
 }
@@ -371,6 +376,8 @@ StepArgs step_args(const Plan& p, void* ws, int batch, const float* wavelet, int
   a.ext_lam = p.ext_h >= 0 ? at<float>(ws, p.L.xlam) : nullptr;
   a.ext_D = p.ext_h >= 0 ? at<float>(ws, p.L.xD) : nullptr;
   a.ext_T = p.ext_T;
+  a.bu = p.born ? at<float>(ws, p.L.bu) : nullptr;
+  a.bw = p.born ? at<float>(ws, p.L.bw) : nullptr;
   return a;
 }
 
@@ -506,13 +513,15 @@ int upload_tables(const Plan& p, void* ws, hipStream_t s) {
 }
 
 // prepares the workspace for a call: tables, cleared error flag, w = dt^2 v^2/h^2
-int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s) {
+// (and the Born source factor 2 dv / v when dv is given)
+int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s, const float* dv = nullptr) {
   int rc = upload_tables(p, ws, s);
   if (rc) return rc;
   Header* hd = at<Header>(ws, p.L.hdr);
   HIP_TRY(launch_set(&hd->err, 0, s));
   const float vmax = (float)(FWI_CFL_LIMIT * p.dx / p.dt);  // device check in FP32
   HIP_TRY(launch_prep(p.d, v, at<float>(ws, p.L.w), p.dt, p.dx, vmax, &hd->err, s));
+  if (p.born && dv) HIP_TRY(launch_prep_born(p.d, v, dv, at<float>(ws, p.L.bw), s));
   return FWI_OK;
 }
 
@@ -520,6 +529,9 @@ int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int
                   hipStream_t s) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
   HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1, s));
+  if (flags & kFwdBorn)
+    HIP_TRY(launch_fill_slots(at<float>(ws, p.L.bu), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1,
+                              s));
   return run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
 }
 
@@ -618,7 +630,8 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   else PFs = {1, 3, 7};
   if (ex && ex->prefetch_reverse > 0) RFs = {ex->prefetch_reverse};
   else RFs = {1, 3};
-  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE);
+  const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
+                     what == FWI_WS_GNHVP);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
   const int nsteps = 16;
   // best of two timings of `nsteps` launches, to keep the choice stable
@@ -685,8 +698,10 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   Hasher h;
   h.pod(*g);
   h.pod(geo->nshot);
-  // an extended-image call runs the gradient's sweeps: tune them once for both
-  if (what == FWI_WS_EXTIMAGE) what = FWI_WS_GRADIENT;
+  // extended-image and Gauss-Newton calls run the gradient's sweeps, Born
+  // modelling the forward's: tune them once for each pair
+  if (what == FWI_WS_EXTIMAGE || what == FWI_WS_GNHVP) what = FWI_WS_GRADIENT;
+  if (what == FWI_WS_BORN) what = FWI_WS_FORWARD;
   std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
                              (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0),
                              (uint64_t)(ex ? ex->prefetch_reverse : 0)};
@@ -865,7 +880,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   int rc = check_inputs(grid, geom);
   if (rc) return rc;
   if (!chosen) return fail(FWI_ERR_ARG, "chosen must not be NULL");
-  if (what < FWI_WS_FORWARD || what > FWI_WS_EXTIMAGE || what == FWI_WS_PRECOND)
+  if (what < FWI_WS_FORWARD || what > FWI_WS_GNHVP || what == FWI_WS_PRECOND)
     return fail(FWI_ERR_ARG, "bad `what`");
   const int plain = exec && exec->mode == FWI_EXEC_PLAIN;
   ExecChoice c = base_choice(grid, geom, exec);
@@ -894,7 +909,7 @@ size_t fwi_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const
                            int hmax) {
   if (what == FWI_WS_PRECOND) return sizeof(Header);
   if (check_inputs(grid, geom)) return 0;
-  if (what < FWI_WS_FORWARD || what > FWI_WS_EXTIMAGE) {
+  if (what < FWI_WS_FORWARD || what > FWI_WS_GNHVP) {
     fail(FWI_ERR_ARG, "bad `what`");
     return 0;
   }
@@ -909,38 +924,55 @@ size_t fwi_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const
   return p->L.total;
 }
 
-int fwi_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
-                const float* wavelet, int64_t wavelet_stride, float* data, void* workspace, size_t ws_bytes,
-                void* hip_stream) {
+static int forward_impl(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                        const float* wavelet, int64_t wavelet_stride, const float* dv, float* data,
+                        void* workspace, size_t ws_bytes, hipStream_t s) {
+  // dv != null: Born modelling, the recorded traces are those of the perturbation wavefield
   int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
   if (rc) return rc;
   if (!data && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "data must not be NULL");
-  hipStream_t s = (hipStream_t)hip_stream;
+  const int what = dv ? FWI_WS_BORN : FWI_WS_FORWARD;
   std::shared_ptr<Plan> p;
   {
     std::shared_ptr<Plan> sz;
-    if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = get_plan(grid, geom, exec, what, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
     if ((rc = ws_check(*sz, ws_bytes))) return rc;
   }
-  if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, workspace, ws_bytes, v, wavelet, wavelet_stride, s, p,
-                     false)))
+  if ((rc = get_plan(grid, geom, exec, what, workspace, ws_bytes, v, wavelet, wavelet_stride, s, p, false)))
     return rc;
   if ((rc = ws_check(*p, ws_bytes))) return rc;
   if (geom->nshot == 0) return FWI_OK;
-  if ((rc = begin_call(*p, workspace, v, s))) return rc;
+  if ((rc = begin_call(*p, workspace, v, s, dv))) return rc;
   for (int b = 0; b < p->nbatch; ++b)
-    if ((rc = forward_batch(*p, workspace, b, kFwdRecord, wavelet, wavelet_stride, s))) return rc;
+    if ((rc = forward_batch(*p, workspace, b, kFwdRecord | (dv ? kFwdBorn : 0), wavelet, wavelet_stride, s)))
+      return rc;
   HIP_TRY(launch_traces_out(at<float>(workspace, p->L.traces), p->ntrace, p->nt_max,
                             at<ShotDesc>(workspace, p->L.shots), at<int32_t>(workspace, p->L.trace_shot), data,
                             s));
   return FWI_OK;
 }
 
+int fwi_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                const float* wavelet, int64_t wavelet_stride, float* data, void* workspace, size_t ws_bytes,
+                void* hip_stream) {
+  return forward_impl(grid, geom, exec, v, wavelet, wavelet_stride, nullptr, data, workspace, ws_bytes,
+                      (hipStream_t)hip_stream);
+}
+
+int fwi_born(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+             const float* wavelet, int64_t wavelet_stride, const float* dv, float* data, void* workspace,
+             size_t ws_bytes, void* hip_stream) {
+  if (!dv) return fail(FWI_ERR_ARG, "dv must not be NULL");
+  return forward_impl(grid, geom, exec, v, wavelet, wavelet_stride, dv, data, workspace, ws_bytes,
+                      (hipStream_t)hip_stream);
+}
+
 static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
                          const float* wavelet, int64_t wstride, const float* d_obs, int misfit, double* J,
                          const double* grad_scale, float* grad, float* illum, int hmax, int rcv_model,
                          float* offset_diag, void* ws, size_t ws_bytes, hipStream_t s, int part,
-                         float* image = nullptr, int ext_h = -1) {
+                         float* image = nullptr, int ext_h = -1, const float* dv = nullptr) {
+  // dv != null (part 0 only): Gauss-Newton product, the Born data J dv act as the residual
   // part: 0 = whole gradient, 1 = forward half (split), 2 = backward half (split);
   // image != null (part 0 only): also the offset-extended image for |h| <= ext_h
   int rc = common_checks(grid, geom, v, wavelet, wstride, ws);
@@ -950,11 +982,14 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
   if (ext && (part != 0 || ext_h < 0 || ext_h > 32 || ext_h >= grid->nx))
     return fail(FWI_ERR_ARG, "image hmax must be in [0, 32] and < nx");
   if (!ext) ext_h = -1;
-  const int what = ext ? FWI_WS_EXTIMAGE : (part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD);
+  const bool gn = dv != nullptr;
+  if (gn && (part != 0 || ext)) return fail(FWI_ERR_ARG, "Gauss-Newton products run as one call");
+  const int what = gn ? FWI_WS_GNHVP : ext ? FWI_WS_EXTIMAGE : (part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD);
   if (part != 2) {
     if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL) return fail(FWI_ERR_ARG, "bad misfit");
     if (!J) return fail(FWI_ERR_ARG, "J must not be NULL");
-    if (!d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "d_obs must not be NULL");
+    if (!gn && !d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0)
+      return fail(FWI_ERR_ARG, "d_obs must not be NULL");
   }
   if (part != 1 && !grad && !ext) return fail(FWI_ERR_ARG, "grad must not be NULL");
   std::shared_ptr<Plan> p;
@@ -983,7 +1018,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
   Header* hd = at<Header>(ws, cp.L.hdr);
 
   if (part != 2) {
-    if ((rc = begin_call(*p, ws, v, s))) return rc;
+    if ((rc = begin_call(*p, ws, v, s, dv))) return rc;
     if (part == 1) {
       p->fwd_ws = nullptr;
     }
@@ -996,8 +1031,9 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
   }
   for (int b = 0; b < cp.nbatch; ++b) {
     if (part != 2) {
-      if ((rc = forward_batch(*p, ws, b, kFwdRecord | kFwdCkpt, wavelet, wstride, s))) return rc;
-      if ((rc = misfit_batch(*p, ws, b, d_obs, misfit, s))) return rc;
+      if ((rc = forward_batch(*p, ws, b, kFwdRecord | kFwdCkpt | (gn ? kFwdBorn : 0), wavelet, wstride, s)))
+        return rc;
+      if ((rc = misfit_batch(*p, ws, b, gn ? nullptr : d_obs, misfit, s))) return rc;
     }
     if (part == 0) {
       if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s))) return rc;
@@ -1044,6 +1080,14 @@ int fwi_extended_image(const fwi_grid* grid, const fwi_geometry* geom, const fwi
   if (!image) return fail(FWI_ERR_ARG, "image must not be NULL");
   return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, nullptr, 0,
                        FWI_RCV_PM, nullptr, workspace, ws_bytes, (hipStream_t)hip_stream, 0, image, hmax);
+}
+
+int fwi_gn_hvp(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+               const float* wavelet, int64_t wavelet_stride, const float* dv, int misfit, double* J, float* hv,
+               void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!dv || !hv) return fail(FWI_ERR_ARG, "dv and hv must not be NULL");
+  return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, nullptr, misfit, J, nullptr, hv, nullptr, 0,
+                       FWI_RCV_PM, nullptr, workspace, ws_bytes, (hipStream_t)hip_stream, 0, nullptr, -1, dv);
 }
 
 int fwi_misfit_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
