@@ -54,6 +54,8 @@ def parse():
                     help="shorten every record to NT samples (counter-collection runs; 0 = full)")
     ap.add_argument("--ext", type=int, default=-1,
                     help="also time the offset-extended image for |h| <= EXT against the plain gradient call")
+    ap.add_argument("--gn", action="store_true",
+                    help="also time the Gauss-Newton Hessian-vector product against the plain gradient call")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
                          "S,TZ,graph_steps,prefetch,prefetch_reverse")
@@ -155,6 +157,32 @@ def time_extended_image(args, grid, geom, w, d_obs, ex, dev):
             "ms_per_call": 1e3 * res["extended_image"], "gradient_ms_per_call": 1e3 * res["gradient"],
             "overhead_vs_gradient": res["extended_image"] / res["gradient"] - 1.0,
             "model_cell_steps_per_s": float(np.sum(nt - 1)) * grid.nz * grid.nx / res["extended_image"]}
+
+
+def time_gn_hvp(args, grid, geom, w, d_obs, ex, dev):
+    """fwi_gn_hvp against fwi_gradient on the same workload and launch
+    configuration (the product adds the Born field to the forward sweep)."""
+    import torch
+    from paper_1406_1864_amd import binding as B
+    from paper_1406_1864_amd.synthetic import bump_direction
+    dv = torch.tensor(bump_direction(grid.nz, grid.nx) * 50.0, dtype=torch.float32, device=dev)
+    ws_g = B.workspace(grid, geom, B.WS_GRADIENT, ex, device=dev)
+    ws_h = B.workspace(grid, geom, B.WS_GNHVP, ex, device=dev)
+    res = {}
+    for name, fn in (("gradient", lambda: B.gradient(w.v_start, w.wavelet, grid, geom, d_obs, "int", ex,
+                                                      illum=False, ws=ws_g, device=dev)),
+                     ("gn_hvp", lambda: B.gn_hvp(w.v_start, w.wavelet, grid, geom, dv, "int", ex, ws=ws_h,
+                                                 device=dev))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    return {"value": geom.nshot / res["gn_hvp"], "unit": "shot-products/s", "ms_per_call": 1e3 * res["gn_hvp"],
+            "gradient_ms_per_call": 1e3 * res["gradient"],
+            "overhead_vs_gradient": res["gn_hvp"] / res["gradient"] - 1.0}
 
 
 def main():
@@ -337,6 +365,8 @@ def main():
 
     if args.ext >= 0:
         out["extended_image"] = time_extended_image(args, grid, geom, w, d_obs, ex, dev)
+    if args.gn:
+        out["gn_hvp"] = time_gn_hvp(args, grid, geom, w, d_obs, ex, dev)
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded

@@ -336,6 +336,63 @@ def illumination(v, grid, geom, wavelet, shots=None):
     return out
 
 
+def gradient_eq3_literal(v, grid, geom, wavelet, d_obs, shots=None):
+    """Eq. (3) taken literally: the source wavefield u itself (not its second
+    time derivative) correlated with the adjoint wavefield of the *plain*
+    residual, in the discrete form whose difference from the exact eq. (2)
+    gradient is a pure end-of-record term:
+
+        g3(x) = -(2/v^3) dt^2 sum_s sum_n u_s[n](x) lam_r,s[n+1](x),
+
+    lam_r the adjoint of ``adjoint`` driven by psi = r (W_d = I).  Summing the
+    exact gradient by parts twice in time gives
+        g_int = g3 + (2/v^3) sum_s sum_n u_s[n] eps_s[n],
+    eps_s the adjoint driven only at n = nt-1 by dt R[nt-1] = dt^2 sum_n r[n]
+    (the record does not end at rest), which ``end_of_record_term`` returns.
+    Returns (J_int, g3)."""
+    v = np.asarray(v, np.float64)
+    shots = range(geom.nshot) if shots is None else shots
+    nz, nx, N = grid.nz, grid.nx, grid.nsponge
+    J = 0.0
+    G = np.zeros_like(v)
+    for s in shots:
+        a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+        shot = geom.shot(s)
+        nt = shot[4]
+        w = np.asarray(wavelet[s] if np.ndim(wavelet) == 2 else wavelet, np.float64)
+        hist = []
+        traces = forward(v, grid, shot, w, keep=hist)          # hist[n + 1] = u[n]
+        Js, _ = misfit_time_integral(traces, d_obs[a:b, :nt], grid.dt)
+        _, r = misfit_l2(traces, d_obs[a:b, :nt])
+        J += Js
+        for m, lam in adjoint(v, grid, shot, r):
+            G += hist[m][N:N + nz, N:N + nx] * lam[N:N + nz, N:N + nx]     # u[m-1] lam[m]
+    return J, -(2.0 / v ** 3) * grid.dt ** 2 * G
+
+
+def end_of_record_term(v, grid, geom, wavelet, d_obs, shots=None):
+    """(2/v^3) sum_s sum_n u_s[n] eps_s[n]: the adjoint eps is driven only at
+    the last sample, by dt R[nt-1] at each receiver (eq. (2) integral of the
+    whole residual trace)."""
+    v = np.asarray(v, np.float64)
+    shots = range(geom.nshot) if shots is None else shots
+    nz, nx, N = grid.nz, grid.nx, grid.nsponge
+    G = np.zeros_like(v)
+    for s in shots:
+        a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+        shot = geom.shot(s)
+        nt = shot[4]
+        w = np.asarray(wavelet[s] if np.ndim(wavelet) == 2 else wavelet, np.float64)
+        hist = []
+        traces = forward(v, grid, shot, w, keep=hist)
+        r = traces - np.asarray(d_obs[a:b, :nt], np.float64)
+        src = np.zeros_like(r)
+        src[:, nt - 1] = grid.dt * grid.dt * np.sum(r, axis=-1)
+        for m, eps in adjoint(v, grid, shot, src):
+            G += hist[m + 1][N:N + nz, N:N + nx] * eps[N:N + nz, N:N + nx]   # u[m] eps[m]
+    return 2.0 / v ** 3 * G
+
+
 def forward_traces(v, grid, geom, wavelet, shots=None):
     """Traces [ntrace][nt_max] of all (or the given) shots, zero past nt_s."""
     shots = list(range(geom.nshot)) if shots is None else list(shots)

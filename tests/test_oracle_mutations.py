@@ -170,3 +170,23 @@ def test_born_missing_factor_is_caught(monkeypatch, tiny):
         return orig(v, grid, shot, wavelet, 0.5 * np.asarray(dv))
     plant(monkeypatch, hs, "born_shot", half)
     fails(P.test_born_is_the_complex_step_derivative, tiny)
+
+
+def test_eq3_unshifted_pairing_is_caught(monkeypatch, tiny):
+    """u[m] paired with lam[m] instead of u[m-1] with lam[m]."""
+    def unshifted(v, grid, geom, wavelet, d_obs, shots=None):
+        v = np.asarray(v, np.float64)
+        N, nz, nx = grid.nsponge, grid.nz, grid.nx
+        J, G = 0.0, np.zeros_like(v)
+        for s in range(geom.nshot):
+            a, b = int(geom.rec_ptr[s]), int(geom.rec_ptr[s + 1])
+            shot = geom.shot(s)
+            hist = []
+            traces = ac.forward(v, grid, shot, np.asarray(wavelet, np.float64), keep=hist)
+            J += ac.misfit_time_integral(traces, d_obs[a:b, :shot[4]], grid.dt)[0]
+            r = traces - d_obs[a:b, :shot[4]]
+            for m, lam in ac.adjoint(v, grid, shot, r):
+                G += hist[m + 1][N:N + nz, N:N + nx] * lam[N:N + nz, N:N + nx]
+        return J, -(2.0 / v ** 3) * grid.dt ** 2 * G
+    plant(monkeypatch, ac, "gradient_eq3_literal", unshifted)
+    fails(P.test_eq3_literal_plus_end_of_record_term_is_the_exact_gradient, tiny)

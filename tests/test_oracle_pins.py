@@ -399,6 +399,37 @@ def test_gn_hvp_equals_jacobian_products(tiny, jac, kind):
     assert float(np.sum(dv * Hdv)) == pytest.approx(2.0 * Jb, rel=1e-10)
 
 
+def test_eq3_literal_plus_end_of_record_term_is_the_exact_gradient(tiny):
+    """Summation by parts twice in time: the exact eq. (2) gradient equals the
+    literal eq. (3) correlation of u with the plain-residual adjoint plus the
+    end-of-record term, whatever the record."""
+    w = tiny
+    d_obs = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
+    J, g, _ = oracle.gradient(w.v_start, w.grid, w.geom, w.wavelet, d_obs, "int")
+    J3, g3 = oracle.gradient_eq3_literal(w.v_start, w.grid, w.geom, w.wavelet, d_obs)
+    E = oracle.end_of_record_term(w.v_start, w.grid, w.geom, w.wavelet, d_obs)
+    assert J3 == pytest.approx(J, rel=1e-14)
+    assert np.max(np.abs(g - g3 - E)) <= 1e-10 * np.max(np.abs(g))
+    assert np.linalg.norm(E) > 1e-3 * np.linalg.norm(g)        # the term is not negligible here
+
+
+def test_eq3_literal_is_exact_when_the_residual_integrates_to_zero(tiny):
+    """With every residual trace summing to zero (R[nt-1] = 0) the end-of-
+    record term vanishes and eq. (3) taken literally is the exact gradient."""
+    w = tiny
+    d_syn = oracle.forward_traces(w.v_start, w.grid, w.geom, w.wavelet)
+    rng = np.random.default_rng(5)
+    delta = rng.standard_normal(d_syn.shape) * 1e-3 * np.max(np.abs(d_syn))
+    delta[:, 0] = 0.0
+    delta[:, 1:] -= delta[:, 1:].mean(axis=-1, keepdims=True)
+    d_obs = d_syn - delta
+    _, g, _ = oracle.gradient(w.v_start, w.grid, w.geom, w.wavelet, d_obs, "int")
+    _, g3 = oracle.gradient_eq3_literal(w.v_start, w.grid, w.geom, w.wavelet, d_obs)
+    E = oracle.end_of_record_term(w.v_start, w.grid, w.geom, w.wavelet, d_obs)
+    assert np.max(np.abs(E)) <= 1e-12 * np.max(np.abs(g))
+    assert np.max(np.abs(g - g3)) <= 1e-10 * np.max(np.abs(g))
+
+
 EXT_CELLS = [(8, 12, 2), (8, 12, -2), (5, 9, 1), (11, 15, -1), (2, 2, 2), (14, 21, -2), (0, 5, 1), (15, 18, 0)]
 
 
