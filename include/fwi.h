@@ -118,7 +118,9 @@ typedef struct {
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
 enum { FWI_MISFIT_L2 = 0,              /* section 2, W_d = I                   */
-       FWI_MISFIT_TIME_INTEGRAL = 1 }; /* eq. (2), W_d u = dt * running sum     */
+       FWI_MISFIT_TIME_INTEGRAL = 1,   /* eq. (2), W_d u = dt * running sum     */
+       FWI_MISFIT_EQ3_LITERAL = 2 };   /* J of eq. (2), grad = eq. (3) taken
+                                          literally (fwi_gradient only)         */
 enum { FWI_HESS_EQ1 = 0,               /* eq. (1): H1 = sum_s E_s              */
        FWI_HESS_OFFSET = 1 };          /* offset diagonal D[2H+1][nz][nx]      */
 enum { FWI_RCV_PM = 0,                 /* Plessix-Mulder aperture factor A_s   */
@@ -175,6 +177,12 @@ int fwi_forward(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *
  *               D(x, h) = (4/v(x)^6) sum_s E_s(x + h) A_s(x - h), h in cells
  *               along x, terms leaving the model are 0 (section 3, diagonal
  *               part); rcv_model selects A_s                                  */
+/* With misfit = FWI_MISFIT_EQ3_LITERAL, J is that of eq. (2) but grad is
+ * eq. (3) taken literally -- u itself correlated with the adjoint of the
+ * plain residual: grad = -(2/v^3) dt^2 sum_s sum_n u[n] lam_r[n+1].  It differs
+ * from the exact eq. (2) gradient by an end-of-record term (the adjoint of
+ * dt^2 sum_n r[n] injected at the last sample), which vanishes when every
+ * residual trace integrates to zero. */
 int fwi_gradient(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
                  const float *v, const float *wavelet, int64_t wavelet_stride,
                  const float *d_obs, int misfit,

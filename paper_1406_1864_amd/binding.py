@@ -41,8 +41,9 @@ RCV_PM, RCV_NONE = 0, 1
 PRECOND_SHOT, PRECOND_OFFSET = 0, 1
 WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND, WS_EXTIMAGE, WS_BORN, WS_GNHVP = range(8)
 
+MISFIT_EQ3_LITERAL = 2
 _MISFIT = {"l2": MISFIT_L2, "int": MISFIT_TIME_INTEGRAL, "time_integral": MISFIT_TIME_INTEGRAL,
-           0: 0, 1: 1}
+           "eq3": MISFIT_EQ3_LITERAL, 0: 0, 1: 1, 2: 2}
 _RCV = {"pm": RCV_PM, "none": RCV_NONE, 0: 0, 1: 1}
 
 

@@ -107,6 +107,10 @@ struct ExtArgs {
   const int32_t* err;
 };
 
+// reverse-kernel variants: kRevExt keeps lam and D for extended imaging;
+// kRevImgU correlates lam[m] with u[m-1] instead of D[m] (eq. (3) taken literally)
+enum : int { kRevExt = 1, kRevImgU = 2 };
+
 // forward-kernel feature flags
 // kFwdBorn: also step the Born perturbation wavefield and record it instead of u
 enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8 };
@@ -146,8 +150,8 @@ hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const S
                              int S, int use_cs, hipStream_t s);
 // prefetch: rows of loads in flight ahead of the sweep (forward 1, 3, 7; reverse 1, 3)
 hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s);
-// ext: also keep lam[m] and D[m] for extended imaging (StepArgs::ext_*)
-hipError_t launch_reverse(const StepArgs& a, int prefetch, bool ext, hipStream_t s);
+// flags: 0, kRevExt (StepArgs::ext_* set) or kRevImgU
+hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s);
 hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
 hipError_t launch_ext_out(const Dims& d, const float* Iacc, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s);
@@ -156,8 +160,9 @@ hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s);
 hipError_t launch_misfit(const MisfitArgs& a, int S, int max_nrec, hipStream_t s);
 hipError_t launch_reduce_J(const double* part, int n, double* J, const int32_t* err, hipStream_t s);
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s);
+// grad = fac * scale * (2/v^3) * sum over slots
 hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const float* v,
-                               const double* scale, float* grad, const int32_t* err, hipStream_t s);
+                               const double* scale, double fac, float* grad, const int32_t* err, hipStream_t s);
 hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
                              const int32_t* trace_shot, float* data, hipStream_t s);
 hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int kind,

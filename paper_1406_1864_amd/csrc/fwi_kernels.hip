@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
 //   g += lam[m] D[m],  E += D[m]^2,  D[m] = w (L u[m-1] + f[m-1] e_src)
 // Same register sweep and prefetch as the forward, for two fields.
 // -------------------------------------------------------------------------
-template <int PF, bool EXT>
+template <int PF, bool EXT, bool IMGU>
 __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   constexpr int W = 9 + PF;
   constexpr int R = PF + 1;
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
           const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
           const float D = wv_ * lapU;
           u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - p0[q]);
-          G[mi] = fmaf(lout, D, pg[q]);
+          G[mi] = fmaf(lout, IMGU ? cu : D, pg[q]);
           E[mi] = fmaf(D, D, pe[q]);
           if (EXT) {
             const int64_t xo = ((int64_t)slot * a.ext_T + ext_slot) * d.model + mi;
@@ -642,7 +642,9 @@ __global__ void k_fill_slots(float* base, int64_t stride, int64_t count, const S
 __global__ void k_advance(int32_t* ctr, int32_t by) { *ctr += by; }
 __global__ void k_set(int32_t* ctr, int32_t value) { *ctr = value; }
 
-// misfit of one trace per thread; psi' = psi * h^2/dt^2 written in place
+// misfit of one trace per thread; psi' = psi * h^2/dt^2 written in place.
+// kind 0: J and psi of the plain misfit; 1: of eq. (2); 2: J of eq. (2) with
+// the plain-residual psi (for eq. (3) taken literally)
 __global__ void k_misfit(MisfitArgs a) {
   const SlotInfo si = a.slots[blockIdx.y];
   if (si.shot < 0 || *a.err) return;
@@ -675,7 +677,7 @@ __global__ void k_misfit(MisfitArgs a) {
     for (int t = 0; t < nt; ++t) {
       const double rr = (t == 0 ? 0.0 : (double)syn[t * st]) - (obs ? (double)obs[t] : 0.0);
       Rp += a.dt * rr;
-      syn[t * st] = (float)(a.dt * (S - Pn) * a.psi_scale);
+      syn[t * st] = (float)((a.kind == 2 ? rr : a.dt * (S - Pn)) * a.psi_scale);
       Pn += Rp;
     }
   }
@@ -762,13 +764,13 @@ __global__ __launch_bounds__(kEpiTile) void k_epilogue(EpiArgs a) {
 }
 
 __global__ void k_gradient_out(Dims d, const float* gacc, int S, const float* v, const double* scale,
-                               float* grad, const int32_t* err) {
+                               double fac, float* grad, const int32_t* err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.model) return;
   float s = 0.0f;
   for (int k = 0; k < S; ++k) s += gacc[(int64_t)k * d.model + i];
   const double vv = v[i];
-  const double sc = scale ? *scale : 1.0;
+  const double sc = (scale ? *scale : 1.0) * fac;
   grad[i] = (*err) ? NAN : (float)(sc * 2.0 / (vv * vv * vv) * (double)s);
 }
 
@@ -881,14 +883,17 @@ hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_
   }
 }
 
-hipError_t launch_reverse(const StepArgs& a, int prefetch, bool ext, hipStream_t s) {
+hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s) {
   const dim3 grid(step_blocks(a.d, a.S)), block(256);
-  if (ext && (!a.ext_lam || !a.ext_D || a.ext_T < 1)) return hipErrorInvalidValue;
-  switch (prefetch * 2 + (ext ? 1 : 0)) {
-    case 2: hipLaunchKernelGGL((k_reverse<1, false>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_reverse<1, true>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_reverse<3, false>), grid, block, 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_reverse<3, true>), grid, block, 0, s, a); break;
+  if ((flags & kRevExt) && (!a.ext_lam || !a.ext_D || a.ext_T < 1)) return hipErrorInvalidValue;
+  if (flags < 0 || flags > 2) return hipErrorInvalidValue;
+  switch (prefetch * 4 + flags) {
+    case 4: hipLaunchKernelGGL((k_reverse<1, false, false>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_reverse<1, true, false>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_reverse<1, false, true>), grid, block, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_reverse<3, false, false>), grid, block, 0, s, a); break;
+    case 13: hipLaunchKernelGGL((k_reverse<3, true, false>), grid, block, 0, s, a); break;
+    case 14: hipLaunchKernelGGL((k_reverse<3, false, true>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -944,9 +949,9 @@ hipError_t launch_epilogue(const EpiArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const float* v,
-                               const double* scale, float* grad, const int32_t* err, hipStream_t s) {
+                               const double* scale, double fac, float* grad, const int32_t* err, hipStream_t s) {
   hipLaunchKernelGGL(k_gradient_out, dim3(blocks_for(d.model, 256)), dim3(256), 0, s, d, gacc, S, v,
-                     scale, grad, err);
+                     scale, fac, grad, err);
   return hipGetLastError();
 }
 

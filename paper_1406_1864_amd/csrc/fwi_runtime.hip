@@ -415,13 +415,14 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
               int64_t wstride, hipStream_t stream) {
   if (nsteps <= 0) return FWI_OK;
   StepArgs a = step_args(p, ws, batch, wavelet, wstride);
-  // reverse sweeps of an extended-image plan keep lam and D of the last ext_T
-  // steps and fold them into the image after every ext_T steps
-  const bool ext = phase == kPhaseRev && p.ext_h >= 0;
+  // reverse sweeps with kRevExt keep lam and D of the last ext_T steps and
+  // fold them into the extended image after every ext_T steps
+  const bool ext = phase == kPhaseRev && (flags & kRevExt);
+  if (ext && p.ext_h < 0) return fail(FWI_ERR_STATE, "extended image without its buffers");
   ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
     return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
-                              : launch_reverse(args, p.pf_rev, ext, s);
+                              : launch_reverse(args, p.pf_rev, flags, s);
   };
   const int T = p.graph_steps;
   if (T <= 0) {
@@ -552,10 +553,11 @@ int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipSt
   return FWI_OK;
 }
 
-int reverse_batch(Plan& p, void* ws, int b, const float* wavelet, int64_t wstride, hipStream_t s) {
+int reverse_batch(Plan& p, void* ws, int b, const float* wavelet, int64_t wstride, hipStream_t s,
+                  int flags = 0) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
   HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), 2 * p.d.field, 2 * p.d.field, slots, p.S, 0, s));
-  return run_steps(p, ws, b, kPhaseRev, 0, p.batch_nt[b] - 1, wavelet, wstride, s);
+  return run_steps(p, ws, b, kPhaseRev, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
 }
 
 int epilogue_batch(Plan& p, void* ws, int b, const float* v, float* H1, float* D, int hmax,
@@ -984,9 +986,12 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
   if (!ext) ext_h = -1;
   const bool gn = dv != nullptr;
   if (gn && (part != 0 || ext)) return fail(FWI_ERR_ARG, "Gauss-Newton products run as one call");
+  // eq. (3) taken literally is not the gradient of J: fwi_gradient only
+  const bool eq3 = part != 2 && misfit == FWI_MISFIT_EQ3_LITERAL;
+  if (eq3 && (part != 0 || ext || gn)) return fail(FWI_ERR_ARG, "FWI_MISFIT_EQ3_LITERAL is for fwi_gradient only");
   const int what = gn ? FWI_WS_GNHVP : ext ? FWI_WS_EXTIMAGE : (part == 0 ? FWI_WS_GRADIENT : FWI_WS_AUTOGRAD);
   if (part != 2) {
-    if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL) return fail(FWI_ERR_ARG, "bad misfit");
+    if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL && !eq3) return fail(FWI_ERR_ARG, "bad misfit");
     if (!J) return fail(FWI_ERR_ARG, "J must not be NULL");
     if (!gn && !d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0)
       return fail(FWI_ERR_ARG, "d_obs must not be NULL");
@@ -1036,7 +1041,8 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
       if ((rc = misfit_batch(*p, ws, b, gn ? nullptr : d_obs, misfit, s))) return rc;
     }
     if (part == 0) {
-      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s))) return rc;
+      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s, (ext ? kRevExt : 0) | (eq3 ? kRevImgU : 0))))
+        return rc;
       if ((rc = epilogue_batch(*p, ws, b, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
     }
   }
@@ -1054,7 +1060,9 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
     }
   }
   if (part != 1 && grad) {
-    HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.S, v, grad_scale, grad, &hd->err, s));
+    // eq. (3) literally: g3 = -(2/v^3) dt^2 sum lam_r[m] u[m-1]
+    HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.S, v, grad_scale, eq3 ? -cp.dt * cp.dt : 1.0, grad,
+                                &hd->err, s));
   }
   if (ext) HIP_TRY(launch_ext_out(cp.d, at<float>(ws, cp.L.xI), ext_h, v, image, &hd->err, s));
   if (part == 1) {

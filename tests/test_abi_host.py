@@ -142,3 +142,16 @@ def test_extended_image_sizing_and_rejects(lib):
     with pytest.raises(B.FwiError) as e:
         B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "int", fake, None, 4, fake, fake, 16, stream=0)
     assert e.value.code == B.FWI_ERR_WORKSPACE
+
+
+def test_eq3_literal_is_gradient_only(lib):
+    """FWI_MISFIT_EQ3_LITERAL is not the gradient of J: the autograd pair and
+    the extended image refuse it before any HIP call."""
+    g, geo = _tiny()
+    fake = 0x1000
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_misfit_forward(g, geo, None, fake, fake, 0, fake, "eq3", fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "eq3", fake, None, 4, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
