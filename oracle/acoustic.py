@@ -32,6 +32,10 @@ boundary or source model.  The discrete readings used here are:
 * sponge: N cells padded outside the model on all four sides by edge
   replication of v; g = (dt/2) eta_max (d/N)^2 with d the max-norm cell
   distance into the sponge and eta_max = 3 v_ref ln(1000) / (2 N h);
+* optional free surface (``grid.free_surface``): no sponge above the model;
+  u = 0 on the padded row just above the model and the three rows above
+  that hold -u of the mirrored model rows (antisymmetric image about that
+  row), so the Laplacian stays symmetric and the adjoint keeps its form;
 * source s[n] = f[n] / h^2 at one cell; receivers record u[n] at cells,
   n = 0 .. nt-1;
 * misfits: J_L2 = 1/2 sum r^2 and J_int = 1/2 sum R^2 with
@@ -107,11 +111,27 @@ class Propagator:
         self.a_minus = 1.0 - g
         self.dt2q = dt * dt * self.q
         self.h = grid.dx
+        self.fs = bool(getattr(grid, "free_surface", False))
+
+    def mirror(self, u):
+        """Free surface: rows above the model replaced by the antisymmetric
+        image about padded row N-1 (which is zero)."""
+        N = self.N
+        g = u.copy()
+        g[..., :N, :] = 0.0
+        for k in range(1, 4):
+            g[..., N - 1 - k, :] = -u[..., N - 1 + k, :]
+        return g
 
     def step(self, u, u_prev, extra):
         """Return u[n+1] from u[n], u[n-1]; ``extra`` is added to L u[n]."""
+        if self.fs:
+            u = self.mirror(u)
         rhs = 2.0 * u - self.a_minus * u_prev + self.dt2q * (laplacian(u, self.h) + extra)
-        return rhs / self.a_plus
+        out = rhs / self.a_plus
+        if self.fs:
+            out[..., :self.N, :] = 0.0           # above the surface: not part of the medium
+        return out
 
     def cell(self, iz, ix):
         return iz + self.N, ix + self.N

@@ -41,6 +41,7 @@ class Grid:
     nt_max: int
     nsponge: int       # absorbing-sponge width N (cells) padded on all 4 sides
     v_ref: float       # sponge reference velocity (m/s), not differentiated
+    free_surface: bool = False   # pressure-free top instead of the top sponge
 
     @property
     def padded(self):

@@ -190,3 +190,16 @@ def test_eq3_unshifted_pairing_is_caught(monkeypatch, tiny):
         return J, -(2.0 / v ** 3) * grid.dt ** 2 * G
     plant(monkeypatch, ac, "gradient_eq3_literal", unshifted)
     fails(P.test_eq3_literal_plus_end_of_record_term_is_the_exact_gradient, tiny)
+
+
+def test_free_surface_mirror_sign_is_caught(monkeypatch):
+    """Even (rigid) image instead of the odd (pressure-free) one."""
+    def even(self, u):
+        N = self.N
+        g = u.copy()
+        g[..., :N, :] = 0.0
+        for k in range(1, 4):
+            g[..., N - 1 - k, :] = u[..., N - 1 + k, :]
+        return g
+    monkeypatch.setattr(ac.Propagator, "mirror", even)
+    fails(P.test_free_surface_is_the_antisymmetric_image)

@@ -106,6 +106,75 @@ def test_reciprocity(tiny):
     assert np.max(np.abs(t_ab - t_ba)) <= 1e-12 * np.max(np.abs(t_ab))
 
 
+# ---------------------------------------------------------------- free surface
+def test_free_surface_is_the_antisymmetric_image():
+    """Method of images, exactly: with the free surface the traces equal
+    those of a medium mirrored about the surface row (no free surface, sponge
+    all round) driven by the source and its negated image."""
+    nz, nx, N, nt = 20, 28, 8, 260
+    v = gaussian_anomaly(nz, nx, 2000.0, 0.15, 4.0, iz0=6, ix0=12).astype(np.float64)
+    fs = Grid(nz, nx, 10.0, 1e-3, nt, N, 2300.0, free_surface=True)
+    # doubled medium: rows 0..nz-1 mirror the model, row nz is the surface,
+    # rows nz+1..2nz are the model
+    v2 = np.concatenate([v[::-1], v[:1], v], axis=0)
+    dbl = Grid(2 * nz + 1, nx, 10.0, 1e-3, nt, N, 2300.0)
+    f = ricker(15.0, 1e-3, nt).astype(np.float64)
+    src, recs = (3, 9), [(0, 2), (1, 20), (5, 13), (19, 27), (12, 0)]
+    got = oracle.forward(v, fs, point_geometry(src, recs, nt).shot(0), f)
+    up = [(nz + 1 + r[0], r[1]) for r in recs]
+    plus = oracle.forward(v2, dbl, point_geometry((nz + 1 + src[0], src[1]), up, nt).shot(0), f)
+    minus = oracle.forward(v2, dbl, point_geometry((nz - 1 - src[0], src[1]), up, nt).shot(0), f)
+    ref = plus - minus
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # and it differs from the absorbing top by the surface reflection
+    absorb = oracle.forward(v, Grid(nz, nx, 10.0, 1e-3, nt, N, 2300.0), point_geometry(src, recs, nt).shot(0), f)
+    assert np.linalg.norm(got - absorb) > 0.1 * np.linalg.norm(absorb)
+
+
+@pytest.fixture(scope="module")
+def tiny_fs():
+    w = tiny_24x16(nt=300)
+    w.grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, w.grid.nt_max, w.grid.nsponge, w.grid.v_ref,
+                  free_surface=True)
+    return w
+
+
+def test_free_surface_dot_product_and_reciprocity(tiny_fs):
+    """The mirrored Laplacian is symmetric: the adjoint keeps its form (dot
+    test) and source/receiver reciprocity holds with the free surface."""
+    w = tiny_fs
+    rng = np.random.default_rng(13)
+    shot = w.geom.shot(0)
+    f = rng.standard_normal(shot[4])
+    d = rng.standard_normal((len(shot[2]), shot[4]))
+    lhs = np.sum(oracle.forward(w.v_true, w.grid, shot, f) * d)
+    rhs = np.sum(f * oracle.source_adjoint(w.v_true, w.grid, shot, d))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    a, b = (0, 3), (9, 19)
+    t_ab = oracle.forward(w.v_true, w.grid, point_geometry(a, [b], 300).shot(0), w.wavelet)
+    t_ba = oracle.forward(w.v_true, w.grid, point_geometry(b, [a], 300).shot(0), w.wavelet)
+    assert np.max(np.abs(t_ab - t_ba)) <= 1e-12 * np.max(np.abs(t_ab))
+
+
+def test_free_surface_gradient_equals_jacobian_transpose_residual(tiny_fs):
+    """g = J^T W^T W r with J by complex step, free surface on."""
+    w = tiny_fs
+    cells = SAMPLE_CELLS[:8]
+    jac = complex_step_jacobian(w, cells)
+    d_obs = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
+    d_syn = oracle.forward_traces(w.v_start, w.grid, w.geom, w.wavelet)
+    J, g, _ = oracle.gradient(w.v_start, w.grid, w.geom, w.wavelet, d_obs, "int")
+    nt = w.grid.nt_max
+    W = w.grid.dt * np.tril(np.ones((nt, nt)))
+    ref = np.zeros(len(cells))
+    for s in range(2):
+        a, b = w.geom.rec_ptr[s], w.geom.rec_ptr[s + 1]
+        r = d_syn[a:b] - d_obs[a:b]
+        ref += np.einsum("krn,rn->k", jac[s], (r @ W.T) @ W)
+    got = np.array([g[c] for c in cells])
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)), (got, ref)
+
+
 def test_time_integral_wavefield_identity(tiny):
     """Section 2: U = int_0^t u solves the wave equation with the integrated
     source H(t) * f; discretely, wavelet dt*cumsum(f) gives dt*cumsum(traces)."""
