@@ -82,6 +82,12 @@ typedef struct {
     int32_t nsponge;    /* sponge width N in cells, >= 4                       */
     double  v_ref;      /* sponge reference velocity (m/s), also the declared
                            maximum velocity used for the CFL check             */
+    int32_t free_surface; /* 0: sponge on all four sides.  1: pressure-free top
+                           (the option of the scheme's reading with a free
+                           surface): no sponge above the model, u = 0 on the
+                           padded row just above model row 0 and the three
+                           rows above it hold -u of the mirrored model rows
+                           (antisymmetric image), for every wavefield        */
 } fwi_grid;
 
 typedef struct {

@@ -55,7 +55,7 @@ class FwiError(RuntimeError):
 
 class fwi_grid(ctypes.Structure):
     _fields_ = [("nz", c_int32), ("nx", c_int32), ("dx", c_double), ("dt", c_double),
-                ("nt_max", c_int32), ("nsponge", c_int32), ("v_ref", c_double)]
+                ("nt_max", c_int32), ("nsponge", c_int32), ("v_ref", c_double), ("free_surface", c_int32)]
 
 
 class fwi_geometry(ctypes.Structure):
@@ -146,7 +146,7 @@ def _i32(a):
 
 def make_grid(grid) -> fwi_grid:
     return fwi_grid(int(grid.nz), int(grid.nx), float(grid.dx), float(grid.dt), int(grid.nt_max),
-                    int(grid.nsponge), float(grid.v_ref))
+                    int(grid.nsponge), float(grid.v_ref), int(bool(getattr(grid, "free_surface", False))))
 
 
 class GeometryC:

@@ -27,6 +27,8 @@ struct Dims {
   int32_t mx0;           // storage column of model column 0 (multiple of 64)
   int32_t XT, ZT, TZ;    // wave tiles along x and z, rows per tile
   int32_t ring;          // floats of one boundary-strip ring: 8 (nx + nz)
+  int32_t fs;            // free surface: rows above the model mirror it (odd image)
+  int32_t ztop;          // first computed padded row: N with a free surface, else 0
   int64_t field;         // floats per field level: Z * P
   int64_t model;         // floats per model-grid array: nz * nx
 };
@@ -113,7 +115,8 @@ enum : int { kRevExt = 1, kRevImgU = 2 };
 
 // forward-kernel feature flags
 // kFwdBorn: also step the Born perturbation wavefield and record it instead of u
-enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8 };
+// (kFwdFS, the free-surface variant, is chosen by the launcher from Dims::fs)
+enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8, kFwdFS = 16 };
 
 struct MisfitArgs {
   const SlotInfo* slots;

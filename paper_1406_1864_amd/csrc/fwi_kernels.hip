@@ -105,6 +105,18 @@ __device__ __forceinline__ Col make_col(const Dims& d, int xs0, int lane) {
   return c;
 }
 
+// Free surface: a row above the model reads the odd image of the model rows
+// about padded row N-1 (itself never written, so it stays 0).  Returns the
+// row to load and its sign.
+__device__ __forceinline__ int image_row(const Dims& d, int r, float& sg) {
+  sg = 1.0f;
+  if (d.fs && r < d.N - 1) {
+    sg = -1.0f;
+    return 2 * (d.N - 1) - r;
+  }
+  return r;
+}
+
 // Uniform classification of one padded row.
 struct Row {
   int mz;      // model row
@@ -174,6 +186,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   constexpr int R = PF + 1;  // point-wise ring; W % R == 0 keeps slots static
   static_assert(W % R == 0, "prefetch distance must make the rings commensurate");
   constexpr bool BORN = (FLAGS & kFwdBorn) != 0;
+  constexpr bool FS = (FLAGS & kFwdFS) != 0;
   __shared__ float lds_all[kWavesPerBlock][kWave + 2 * kRadius];
   __shared__ float ldsB_all[kWavesPerBlock][BORN ? kWave + 2 * kRadius : 1];
   const int lane = threadIdx.x & 63;
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   const int xt = tile % d.XT, zt = tile / d.XT;
   const int xs0 = xt * kWave;
   const Col col = make_col(d, xs0, lane);
-  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
+  const int z0 = (FS ? d.ztop : 0) + zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
   float* ubase = a.u + (int64_t)si.cs * kULevels * d.field;
   const float* ucur = ubase + (int64_t)(n & 1) * d.field;
   float* unxt = ubase + (int64_t)((n + 1) & 1) * d.field;
@@ -261,10 +274,29 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
     p = binc[idx];
     f = a.bw[idx];
   };
+  // Only the first window of the top tile reaches above the model; with a
+  // free surface it reads the odd image there.  Elsewhere the loads are issued
+  // back to back and consumed later in the sweep.
+  if (FS && z0 == d.ztop) {
 #pragma unroll
-  for (int j = 0; j < 8 + PF; ++j) {
-    load_row(z0 - 4 + j, wc[j], wh[j]);
-    if (BORN) load_brow(z0 - 4 + j, bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
+    for (int j = 0; j < 8 + PF; ++j) {
+      float sg;
+      const int r = image_row(d, z0 - 4 + j, sg);
+      load_row(r, wc[j], wh[j]);
+      wc[j] *= sg;
+      wh[j] *= sg;
+      if (BORN) {
+        load_brow(r, bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
+        bc[j % (BORN ? W : 1)] *= sg;
+        bh[j % (BORN ? W : 1)] *= sg;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8 + PF; ++j) {
+      load_row(z0 - 4 + j, wc[j], wh[j]);
+      if (BORN) load_brow(z0 - 4 + j, bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
+    }
   }
 #pragma unroll
   for (int j = 0; j < PF; ++j)
@@ -361,7 +393,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
 //   g += lam[m] D[m],  E += D[m]^2,  D[m] = w (L u[m-1] + f[m-1] e_src)
 // Same register sweep and prefetch as the forward, for two fields.
 // -------------------------------------------------------------------------
-template <int PF, bool EXT, bool IMGU>
+template <int PF, bool EXT, bool IMGU, bool FS>
 __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   constexpr int W = 9 + PF;
   constexpr int R = PF + 1;
@@ -387,7 +419,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const Col col = make_col(d, xs0, lane);
   const int hmx = col.hcol - d.mx0;
   const bool hmcol = hmx >= 0 && hmx < d.nx;
-  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
+  const int z0 = (FS ? d.ztop : 0) + zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
   float* ubase = a.u + (int64_t)si.cs * kULevels * d.field;
   float* u_m = ubase + (int64_t)(m & 1) * d.field;  // u[m] in, u[m-2] out
   const float* u_m1 = ubase + (int64_t)((m - 1) & 1) * d.field;
@@ -462,8 +494,22 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
       u0 = g = e = 0.0f;
     }
   };
+  // only the first window of the top tile reaches above the model (free
+  // surface: odd image); elsewhere the loads go out back to back
+  if (FS && z0 == d.ztop) {
 #pragma unroll
-  for (int j = 0; j < 8 + PF; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+    for (int j = 0; j < 8 + PF; ++j) {
+      float sg;
+      load_rows(image_row(d, z0 - 4 + j, sg), uc[j], uh[j], lc[j], lh[j]);
+      uc[j] *= sg;
+      uh[j] *= sg;
+      lc[j] *= sg;
+      lh[j] *= sg;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8 + PF; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+  }
 #pragma unroll
   for (int j = 0; j < PF; ++j)
     if (z0 + j < z1) load_pt(z0 + j, p0[j], pl[j], pw[j], pg[j], pe[j]);
@@ -852,22 +898,23 @@ hipError_t launch_fill_slots(float* base, int64_t stride, int64_t count, const S
   return hipGetLastError();
 }
 
+// the free-surface variant is a separate instantiation, so that the sweeps
+// without one carry no trace of it
+template <int FLAGS, int PF>
+static void forward_fs(const StepArgs& a, hipStream_t s) {
+  const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  if (a.d.fs) hipLaunchKernelGGL((k_forward<FLAGS | kFwdFS, PF>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_forward<FLAGS, PF>), grid, block, 0, s, a);
+}
+
 template <int PF>
 static hipError_t launch_forward_pf(const StepArgs& a, int flags, hipStream_t s) {
-  const dim3 grid(step_blocks(a.d, a.S)), block(256);
   switch (flags) {
-    case 0: hipLaunchKernelGGL((k_forward<0, PF>), grid, block, 0, s, a); break;
-    case kFwdRecord: hipLaunchKernelGGL((k_forward<kFwdRecord, PF>), grid, block, 0, s, a); break;
-    case kFwdRecord | kFwdCkpt:
-      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt, PF>), grid, block, 0, s, a);
-      break;
-    case kFwdIllum: hipLaunchKernelGGL((k_forward<kFwdIllum, PF>), grid, block, 0, s, a); break;
-    case kFwdRecord | kFwdBorn:
-      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdBorn, PF>), grid, block, 0, s, a);
-      break;
-    case kFwdRecord | kFwdCkpt | kFwdBorn:
-      hipLaunchKernelGGL((k_forward<kFwdRecord | kFwdCkpt | kFwdBorn, PF>), grid, block, 0, s, a);
-      break;
+    case kFwdRecord: forward_fs<kFwdRecord, PF>(a, s); break;
+    case kFwdRecord | kFwdCkpt: forward_fs<kFwdRecord | kFwdCkpt, PF>(a, s); break;
+    case kFwdIllum: forward_fs<kFwdIllum, PF>(a, s); break;
+    case kFwdRecord | kFwdBorn: forward_fs<kFwdRecord | kFwdBorn, PF>(a, s); break;
+    case kFwdRecord | kFwdCkpt | kFwdBorn: forward_fs<kFwdRecord | kFwdCkpt | kFwdBorn, PF>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -883,17 +930,23 @@ hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_
   }
 }
 
-hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s) {
+template <int PF, bool EXT, bool IMGU>
+static void reverse_fs(const StepArgs& a, hipStream_t s) {
   const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  if (a.d.fs) hipLaunchKernelGGL((k_reverse<PF, EXT, IMGU, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_reverse<PF, EXT, IMGU, false>), grid, block, 0, s, a);
+}
+
+hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s) {
   if ((flags & kRevExt) && (!a.ext_lam || !a.ext_D || a.ext_T < 1)) return hipErrorInvalidValue;
   if (flags < 0 || flags > 2) return hipErrorInvalidValue;
   switch (prefetch * 4 + flags) {
-    case 4: hipLaunchKernelGGL((k_reverse<1, false, false>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_reverse<1, true, false>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_reverse<1, false, true>), grid, block, 0, s, a); break;
-    case 12: hipLaunchKernelGGL((k_reverse<3, false, false>), grid, block, 0, s, a); break;
-    case 13: hipLaunchKernelGGL((k_reverse<3, true, false>), grid, block, 0, s, a); break;
-    case 14: hipLaunchKernelGGL((k_reverse<3, false, true>), grid, block, 0, s, a); break;
+    case 4: reverse_fs<1, false, false>(a, s); break;
+    case 5: reverse_fs<1, true, false>(a, s); break;
+    case 6: reverse_fs<1, false, true>(a, s); break;
+    case 12: reverse_fs<3, false, false>(a, s); break;
+    case 13: reverse_fs<3, true, false>(a, s); break;
+    case 14: reverse_fs<3, false, true>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -61,6 +61,17 @@ struct Hasher {
   }
   template <class T>
   void pod(const T& v) { bytes(&v, sizeof(T)); }
+  // field by field: the struct's padding bytes are not part of its value
+  void grid(const fwi_grid& g) {
+    pod(g.nz);
+    pod(g.nx);
+    pod(g.dx);
+    pod(g.dt);
+    pod(g.nt_max);
+    pod(g.nsponge);
+    pod(g.v_ref);
+    pod(g.free_surface);
+  }
 };
 
 // ---------------------------------------------------------------- validation
@@ -72,6 +83,7 @@ int check_inputs(const fwi_grid* g, const fwi_geometry* geo) {
     return fail(FWI_ERR_ARG, "dx and dt must be positive and finite");
   if (g->nt_max < 2) return fail(FWI_ERR_ARG, "nt_max must be >= 2");
   if (g->nsponge < kRadius) return fail(FWI_ERR_ARG, "nsponge must be >= 4");
+  if (g->free_surface != 0 && g->free_surface != 1) return fail(FWI_ERR_ARG, "free_surface must be 0 or 1");
   if (!(g->v_ref > 0.0f) || !std::isfinite(g->v_ref)) return fail(FWI_ERR_ARG, "v_ref must be positive");
   const double courant = (double)g->v_ref * g->dt / g->dx;
   if (courant > FWI_CFL_LIMIT)
@@ -167,7 +179,7 @@ int shot_nt(const fwi_grid* g, const fwi_geometry* geo, int s) { return geo->nt 
 
 uint64_t inputs_hash(const fwi_grid* g, const fwi_geometry* geo) {
   Hasher h;
-  h.pod(*g);
+  h.grid(*g);
   h.pod(geo->nshot);
   if (geo->nshot > 0) {
     h.bytes(geo->src_iz, sizeof(int32_t) * geo->nshot);
@@ -209,7 +221,9 @@ void build_dims(Plan& p, const fwi_grid* g, int TZ) {
   d.P = (int)align_up(d.off + d.X, kWave);
   d.XT = d.P / kWave;
   d.TZ = TZ;
-  d.ZT = (d.Z + TZ - 1) / TZ;
+  d.fs = g->free_surface ? 1 : 0;
+  d.ztop = d.fs ? d.N : 0;
+  d.ZT = (d.Z - d.ztop + TZ - 1) / TZ;
   d.ring = 8 * (d.nx + d.nz);
   d.field = (int64_t)d.Z * d.P;
   d.model = (int64_t)d.nz * d.nx;
@@ -698,7 +712,7 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
 
 std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what) {
   Hasher h;
-  h.pod(*g);
+  h.grid(*g);
   h.pod(geo->nshot);
   // extended-image and Gauss-Newton calls run the gradient's sweeps, Born
   // modelling the forward's: tune them once for each pair
