@@ -239,6 +239,15 @@ int fwi_gn_hvp(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *e
                const float *dv, int misfit, double *J, float *hv,
                void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* The misfit J(v) alone (section 2 / eq. (2)), e.g. for line searches: the
+ * forward sweep with recording and the misfit reduction, no checkpoints.
+ * Arguments as fwi_gradient; J is a device double.
+ * Workspace: fwi_workspace_bytes(..., FWI_WS_FORWARD, 0). */
+int fwi_misfit_value(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                     const float *v, const float *wavelet, int64_t wavelet_stride,
+                     const float *d_obs, int misfit, double *J,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Hessian diagonals from the forward wavefield alone (no adjoint pass).
  *   kind FWI_HESS_EQ1:    diag [nz][nx]            = H1            (eq. (1))
  *   kind FWI_HESS_OFFSET: diag [2*hmax+1][nz][nx]  = D(x, h)       (section 3) */

@@ -84,6 +84,8 @@ _SIGS = {
     "fwi_extended_image": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                    c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p,
                                    c_void_p, c_size_t, c_void_p]),
+    "fwi_misfit_value": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
+                                 c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_born": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
                          c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_gn_hvp": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
@@ -232,6 +234,14 @@ def fwi_extended_image(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, mis
                                             int(ws_bytes), _stream(stream)))
 
 
+def fwi_misfit_value(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J, workspace, ws_bytes,
+                     stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_misfit_value(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v),
+                                          _ptr(wavelet), int(wavelet_stride), _ptr(d_obs), _MISFIT[misfit], _ptr(J),
+                                          _ptr(workspace), int(ws_bytes), _stream(stream)))
+
+
 def fwi_born(grid, geom, exec_, v, wavelet, wavelet_stride, dv, data, workspace, ws_bytes, stream=None):
     g, G = make_grid(grid), _geo(geom)
     return _check(load().fwi_born(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v), _ptr(wavelet),
@@ -366,6 +376,19 @@ def extended_image(v, wavelet, grid, geom, d_obs, hmax, misfit="int", exec_=None
     ws = workspace(grid, G, WS_EXTIMAGE, exec_, hmax, device=device) if ws is None else ws
     fwi_extended_image(grid, G, exec_, vd, w, ws_, dobs, misfit, J, grad, hmax, image, ws, ws.numel())
     return J, grad, image
+
+
+def misfit_value(v, wavelet, grid, geom, d_obs, misfit="int", exec_=None, ws=None, device="cuda"):
+    """J(v) (torch float64 scalar on the device)."""
+    torch = _torch()
+    G = _geo(geom)
+    vd = _dev(v, torch.float32, device)
+    w, ws_ = _wavelet(wavelet, grid.nt_max, device)
+    dobs = _dev(d_obs, torch.float32, device)
+    J = torch.empty((), dtype=torch.float64, device=device)
+    ws = workspace(grid, G, WS_FORWARD, exec_, device=device) if ws is None else ws
+    fwi_misfit_value(grid, G, exec_, vd, w, ws_, dobs, misfit, J, ws, ws.numel())
+    return J
 
 
 def born(v, wavelet, grid, geom, dv, exec_=None, ws=None, device="cuda"):

@@ -975,6 +975,39 @@ int fwi_forward(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* 
                       (hipStream_t)hip_stream);
 }
 
+int fwi_misfit_value(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                     const float* wavelet, int64_t wavelet_stride, const float* d_obs, int misfit, double* J,
+                     void* workspace, size_t ws_bytes, void* hip_stream) {
+  int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
+  if (rc) return rc;
+  if (misfit != FWI_MISFIT_L2 && misfit != FWI_MISFIT_TIME_INTEGRAL) return fail(FWI_ERR_ARG, "bad misfit");
+  if (!J) return fail(FWI_ERR_ARG, "J must not be NULL");
+  if (!d_obs && geom->nshot > 0 && geom->rec_ptr[geom->nshot] > 0) return fail(FWI_ERR_ARG, "d_obs must not be NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::shared_ptr<Plan> p;
+  {
+    std::shared_ptr<Plan> sz;
+    if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, nullptr, 0, nullptr, nullptr, 0, s, sz, true))) return rc;
+    if ((rc = ws_check(*sz, ws_bytes))) return rc;
+  }
+  if ((rc = get_plan(grid, geom, exec, FWI_WS_FORWARD, workspace, ws_bytes, v, wavelet, wavelet_stride, s, p,
+                     false)))
+    return rc;
+  if ((rc = ws_check(*p, ws_bytes))) return rc;
+  if ((rc = begin_call(*p, workspace, v, s))) return rc;
+  for (int b = 0; b < p->nbatch; ++b) {
+    if ((rc = forward_batch(*p, workspace, b, kFwdRecord, wavelet, wavelet_stride, s))) return rc;
+    if ((rc = misfit_batch(*p, workspace, b, d_obs, misfit, s))) return rc;
+  }
+  Header* hd = at<Header>(workspace, p->L.hdr);
+  if (p->ntrace > 0) {
+    HIP_TRY(launch_reduce_J(at<double>(workspace, p->L.jpart), p->ntrace, J, &hd->err, s));
+  } else {
+    HIP_TRY(launch_fill(J, sizeof(double), s));
+  }
+  return FWI_OK;
+}
+
 int fwi_born(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
              const float* wavelet, int64_t wavelet_stride, const float* dv, float* data, void* workspace,
              size_t ws_bytes, void* hip_stream) {

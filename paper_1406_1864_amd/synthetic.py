@@ -255,12 +255,28 @@ def tiny_24x16(nt=400) -> Workload:
                     ricker(10.0, 1e-3, nt).astype(np.float32), 10.0, hmax=2)
 
 
+def layered_256x96(nshot=16, nt=1500) -> Workload:
+    """The layered geology at dx = 50 m for iterative inversions: 256x96 cells
+    (12.8 x 4.8 km), 16-cell sponge, 16 shots at depth 1 (ix = 16k+8), 128
+    receivers (ix = 2k), Ricker 3 Hz, dt = 4 ms, nt = 1500 (6 s).  Start model:
+    Gaussian smoothing, 5 cells (the 250 m of the 1024x384 workload)."""
+    nz, nx, dx = 96, 256, 50.0
+    v_true = layered_model(nz, nx, dx, seed=1406)
+    v_start = smooth(v_true, 5.0)
+    grid = Grid(nz, nx, dx, 4e-3, nt, 16, float(v_true.max()))
+    src = (16 * np.arange(16) + 8)[:nshot]
+    geom = surface_geometry(src, [np.arange(0, 256, 2)] * len(src), 1, 1, nt)
+    return Workload(f"layered_256x96_{nshot}shots_nt{nt}", grid, geom, v_true, v_start,
+                    ricker(3.0, 4e-3, nt).astype(np.float32), 3.0, hmax=8)
+
+
 WORKLOADS = {
     "anomaly_200x100": anomaly_200x100,
     "layered_1024x384": layered_1024x384,
     "ragged_1024x384": ragged_1024x384,
     "autograd_1024x384": autograd_1024x384,
     "offset_2048x768": offset_2048x768,
+    "layered_256x96": layered_256x96,
 }
 
 

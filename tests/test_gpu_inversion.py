@@ -1,0 +1,63 @@
+"""The inversion drivers run on the GPU objective and on an FP64 oracle
+objective from the same start: after two iterations the models agree to the
+gradient tolerance (relative to the model update), for each scaling."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1406_1864_amd import binding as B
+from paper_1406_1864_amd.inversion import GPUObjective, lbfgs, prcg
+from paper_1406_1864_amd.synthetic import tiny_24x16
+
+from helpers import GRAD_TOL, rel, report
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+class OracleObjective:
+    """value / value_grad of the inversion drivers from the FP64 oracle."""
+
+    def __init__(self, w, d_obs, misfit, precond, hmax=2, eps=1e-2):
+        self.w, self.d_obs, self.misfit, self.precond, self.hmax, self.eps = w, d_obs, misfit, precond, hmax, eps
+        self.evals = 0
+
+    def value(self, v):
+        self.evals += 1
+        w = self.w
+        tr = oracle.forward_traces(np.asarray(v, np.float32).astype(np.float64), w.grid, w.geom, w.wavelet)
+        return oracle.misfit(tr, self.d_obs, self.misfit, w.grid.dt)[0]
+
+    def value_grad(self, v):
+        self.evals += 1
+        w = self.w
+        v = np.asarray(v, np.float32).astype(np.float64)
+        J, g, H1, E = oracle.gradient(v, w.grid, w.geom, w.wavelet, self.d_obs, self.misfit, return_parts=True)
+        if self.precond == "none":
+            minv = np.ones_like(g)
+        else:
+            if self.precond == "shot":
+                P = oracle.shot_scaling(v, H1)
+            else:
+                A = [oracle.aperture_factor(w.grid, *w.geom.shot(s)[2:4]) for s in range(w.geom.nshot)]
+                P = oracle.offset_scaling(oracle.offset_diag(v, E, A, self.hmax))
+            minv = oracle.precondition(np.ones_like(g), P, self.eps)
+        return J, g, minv
+
+
+@pytest.mark.parametrize("precond", ["none", "shot", "offset"])
+@pytest.mark.parametrize("driver", [prcg, lbfgs])
+def test_two_iterations_match_the_oracle(precond, driver):
+    w = tiny_24x16(nt=300)
+    d_obs = oracle.forward_traces(w.v_true, w.grid, w.geom, w.wavelet)
+    gpu = GPUObjective(w.grid, w.geom, w.wavelet, d_obs.astype(np.float32), "int", precond, hmax=2)
+    ref = OracleObjective(w, d_obs, "int", precond)
+    v0 = w.v_start.astype(np.float64)
+    vg, hg = driver(gpu, v0, 2, step0=20.0)
+    vr, hr = driver(ref, v0, 2, step0=20.0)
+    tag = f"{driver.__name__} {precond}"
+    assert len(hg) == len(hr) == 3, (hg, hr)
+    assert report(f"inversion {tag} model update", rel(vg - v0, vr - v0), GRAD_TOL) < GRAD_TOL
+    for a, b in zip(hg, hr):
+        assert abs(a["J"] - b["J"]) <= 1e-3 * b["J"]
+    assert hg[-1]["J"] < hg[0]["J"]
