@@ -105,7 +105,9 @@ def measured_traffic(kname, chosen):
         p = json.load(fh)
     if p.get("kernel_source_sha") != kernel_hash():
         return None
-    if any(p["launch_config"].get(k) != chosen.get(k) for k in p["launch_config"]):
+    keys = ("shots_in_flight", "tile_rows", "graph_steps", "prefetch", "prefetch_reverse",
+            "shots_in_flight_reverse", "tile_rows_reverse")
+    if any(p["launch_config"].get(k) != chosen.get(k) for k in keys):
         return None
     return p.get("bytes_per_launch")
 
@@ -236,8 +238,11 @@ def main():
     torch.cuda.synchronize()
     print("# recorded data modelled", file=sys.stderr, flush=True)
     if args.exec:
-        S_, TZ_, G_, PF_, PR_ = (int(x) for x in args.exec.split(","))
-        ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_)
+        vals = [int(x) for x in args.exec.split(",")]
+        S_, TZ_, G_, PF_, PR_ = vals[:5]
+        SR_, TZR_ = (vals[5:7] + [0, 0])[:2] if len(vals) > 5 else (0, 0)
+        ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_,
+                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_)
     else:
         ex = B.make_exec(autotune=1)
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
@@ -293,11 +298,14 @@ def main():
     rev_bytes = float(sum((nt[s] - 1) * reverse_bytes_per_shot_step(grid, int(nrec[s])) for s in range(shots)))
     rev_ms = phase[1] / args.steps
     chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
-    # k_reverse launches per backward: shots run in batches of `shots_in_flight`
-    # (longest records first), each batch for its longest record
+    # k_reverse launches per backward: the forward runs shots in batches of
+    # `shots_in_flight` (longest records first), the reverse takes each batch
+    # `shots_in_flight_reverse` at a time, each group for its longest record
     S = max(1, chosen["shots_in_flight"])
+    Sr = max(1, chosen["shots_in_flight_reverse"])
     order = sorted(range(shots), key=lambda s: -int(nt[s]))
-    launches = sum(int(nt[order[b]]) - 1 for b in range(0, shots, S))
+    launches = sum(int(nt[order[b + j]]) - 1 for b in range(0, shots, S) for j in range(0, S, Sr)
+                   if b + j < shots)
     launch_us = rev_ms * 1e3 / max(launches, 1)
     bytes_per_launch = rev_bytes / max(launches, 1)
     achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
@@ -326,7 +334,9 @@ def main():
                    "misfit": "time_integral", "hmax": HM, "path": "autograd, batched, hipGraph, autotuned",
                    "shots_in_flight": chosen["shots_in_flight"], "tile_rows": chosen["tile_rows"],
                    "graph_steps": chosen["graph_steps"], "prefetch": chosen["prefetch"],
-                   "prefetch_reverse": chosen["prefetch_reverse"]},
+                   "prefetch_reverse": chosen["prefetch_reverse"],
+                   "shots_in_flight_reverse": chosen["shots_in_flight_reverse"],
+                   "tile_rows_reverse": chosen["tile_rows_reverse"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},

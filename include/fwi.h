@@ -107,8 +107,10 @@ typedef struct {
     int32_t mode;             /* FWI_EXEC_BATCHED (default) or FWI_EXEC_PLAIN:
                                  plain = one shot at a time, one launch per
                                  time step, no graph, no autotuning            */
-    int32_t shots_in_flight;  /* shots advanced together by one launch         */
-    int32_t tile_rows;        /* rows of one wavefront's tile (z sweep length) */
+    int32_t shots_in_flight;  /* shots advanced together by one launch of the
+                                 forward sweep                                 */
+    int32_t tile_rows;        /* rows of one wavefront's tile (z sweep length)
+                                 of the forward sweep                          */
     int32_t graph_steps;      /* time steps per captured hipGraph chunk;
                                  -1 = do not use graphs                        */
     int32_t autotune;         /* 1 = pick unset fields by timing a few steps
@@ -120,6 +122,13 @@ typedef struct {
     int32_t prefetch;         /* rows of loads a forward-sweep wavefront keeps
                                  in flight ahead of its z sweep: 1, 3 or 7     */
     int32_t prefetch_reverse; /* same for the fused reverse sweep: 1 or 3      */
+    int32_t shots_in_flight_reverse; /* shots per launch of the reverse sweep;
+                                 it takes each forward batch's shots this many
+                                 at a time, so it must divide shots_in_flight
+                                 (else the forward's value is used);
+                                 0 = tuned, or the forward's                   */
+    int32_t tile_rows_reverse; /* rows per tile of the reverse sweep; 0 =
+                                 tuned, or tile_rows                           */
 } fwi_exec;
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
@@ -149,7 +158,7 @@ size_t fwi_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
                            const fwi_exec *exec, int what, int hmax);
 
 /* The execution settings (shots_in_flight, tile_rows, graph_steps, prefetch,
- * prefetch_reverse) that a
+ * prefetch_reverse, shots_in_flight_reverse, tile_rows_reverse) that a
  * call with these arguments uses: the autotuned choice once tuning has run on
  * the current device, else the heuristic defaults.  Fills *chosen (mode and
  * autotune copied from exec).  Returns 0 or FWI_ERR_*. */

@@ -124,7 +124,7 @@ enum Phase { kPhaseFwd = 0, kPhaseRev = 1 };
 
 struct Layout {
   size_t hdr, shots, slots, rdir, rrows, rmaps, trace_shot;
-  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, bu, bw, total;
+  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, bu, bw, rslots, total;
 };
 
 // device header at the start of every workspace
@@ -139,8 +139,10 @@ struct Plan {
   uint64_t key = 0;
   uint64_t ikey = 0;  // hash of grid + geometry
   Dims d{};
+  Dims dr{};  // the reverse sweep's tiling (its own rows per tile)
   int nshot = 0, ntrace = 0, max_nrec = 0, nt_max = 0;
   int S = 1, nbatch = 0, ncs = 0;
+  int Sr = 1, nrbatch = 0, xcd_map_r = 0;  // reverse sweep: shots in flight, batches
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
   int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
   int ext_h = -1, ext_T = 0;   // extended imaging: offset bound (-1: off), ring of reverse steps
@@ -150,6 +152,11 @@ struct Plan {
   std::vector<ShotDesc> shots;
   std::vector<SlotInfo> slots;  // [nbatch][S]
   std::vector<int> batch_nt;    // longest record of each batch
+  // reverse batches: each forward batch's slots taken Sr at a time (same
+  // checkpoint sets), longest record of each
+  std::vector<SlotInfo> rslots;   // [nrbatch][Sr]
+  std::vector<int> rbatch_nt;
+  std::vector<int> rbatch_begin;  // [nbatch + 1]: reverse batches of forward batch b
   std::vector<RmapDir> rdir;
   std::vector<RmapRow> rrows;
   std::vector<int32_t> rmaps;
@@ -166,8 +173,10 @@ struct Plan {
   }
 };
 
+// Launch configuration: the forward sweep's shots in flight / rows per tile
+// and the reverse sweep's (Sr divides S; 0 = same as the forward's).
 struct ExecChoice {
-  int S, TZ, graph_steps, pf_fwd, pf_rev;
+  int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr;
 };
 
 std::mutex g_mutex;
@@ -243,10 +252,15 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->dx = g->dx;
   p->dt = g->dt;
   p->S = plain ? 1 : std::max(1, std::min(ex.S, std::max(geo->nshot, 1)));
+  p->Sr = (plain || ex.Sr <= 0) ? p->S : std::max(1, std::min(ex.Sr, p->S));
+  if (p->S % p->Sr) p->Sr = p->S;  // validated by the caller; keep the tables consistent
   p->graph_steps = plain ? -1 : ex.graph_steps;
   p->xcd_map = (p->S >= 8 && p->S % 8 == 0) ? 1 : 0;
+  p->xcd_map_r = (p->Sr >= 8 && p->Sr % 8 == 0) ? 1 : 0;
   p->pf_fwd = ex.pf_fwd;
   p->pf_rev = ex.pf_rev;
+  build_dims(*p, g, ex.TZr > 0 ? ex.TZr : ex.TZ);
+  p->dr = p->d;
   build_dims(*p, g, ex.TZ);
   const Dims& d = p->d;
   const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
@@ -314,6 +328,26 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
     p->batch_nt[b] = std::max(p->batch_nt[b], p->shots[shot].nt);
   }
   p->ncs = p->split ? std::max(ns, 1) : p->S;
+  p->rbatch_begin.assign(p->nbatch + 1, 0);
+  for (int b = 0; b < p->nbatch; ++b) {
+    p->rbatch_begin[b] = (int)p->rbatch_nt.size();
+    for (int j = 0; j < p->S; j += p->Sr) {
+      int nt = 0;
+      for (int k = 0; k < p->Sr; ++k) {
+        const SlotInfo si = p->slots[(size_t)b * p->S + j + k];
+        p->rslots.push_back(si);
+        if (si.shot >= 0) nt = std::max(nt, p->shots[si.shot].nt);
+      }
+      if (nt == 0) {  // all idle: drop the group
+        p->rslots.resize(p->rslots.size() - p->Sr);
+        continue;
+      }
+      p->rbatch_nt.push_back(nt);
+    }
+  }
+  p->rbatch_begin[p->nbatch] = (int)p->rbatch_nt.size();
+  p->nrbatch = (int)p->rbatch_nt.size();
+  if (p->rslots.empty()) p->rslots.assign(p->Sr, SlotInfo{-1, 0});
 
   // workspace layout
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
@@ -333,6 +367,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.hdr = take(sizeof(Header));
   L.shots = take(sizeof(ShotDesc) * p->shots.size());
   L.slots = take(sizeof(SlotInfo) * p->slots.size());
+  L.rslots = take(sizeof(SlotInfo) * p->rslots.size());
   L.rdir = take(sizeof(RmapDir) * p->rdir.size());
   L.rrows = take(sizeof(RmapRow) * p->rrows.size());
   L.rmaps = take(sizeof(int32_t) * p->rmaps.size());
@@ -341,15 +376,16 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.traces = take(sizeof(float) * (size_t)g->nt_max * std::max(p->ntrace, 1));
   L.jpart = take(sizeof(double) * std::max(p->ntrace, 1));
   L.u = take(sizeof(float) * kULevels * d.field * p->ncs);
-  L.lam = grad ? take(sizeof(float) * 2 * d.field * p->S) : o;
-  L.g = grad ? take(sizeof(float) * d.model * p->S) : o;
-  L.E = (grad || hess) ? take(sizeof(float) * d.model * p->S) : o;
+  L.lam = grad ? take(sizeof(float) * 2 * d.field * p->Sr) : o;
+  L.g = grad ? take(sizeof(float) * d.model * p->Sr) : o;
+  // E per reverse slot (gradient) or per forward slot (forward-only Hessian)
+  L.E = (grad || hess) ? take(sizeof(float) * d.model * (hess ? p->S : p->Sr)) : o;
   p->snap_stride = grad ? (int64_t)max_nsnap * 2 * d.model : 0;
   p->strip_stride = grad ? (int64_t)g->nt_max * d.ring : 0;
   L.snap = grad ? take(sizeof(float) * p->snap_stride * p->ncs) : o;
   L.strip = grad ? take(sizeof(float) * p->strip_stride * p->ncs) : o;
-  L.xlam = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
-  L.xD = ext ? take(sizeof(float) * d.model * p->ext_T * p->S) : o;
+  L.xlam = ext ? take(sizeof(float) * d.model * p->ext_T * p->Sr) : o;
+  L.xD = ext ? take(sizeof(float) * d.model * p->ext_T * p->Sr) : o;
   L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1)) : o;
   L.bu = p->born ? take(sizeof(float) * kULevels * d.field * p->ncs) : o;
   L.bw = p->born ? take(sizeof(float) * d.field) : o;
@@ -360,12 +396,15 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
 template <class T>
 T* at(void* ws, size_t off) { return (T*)((char*)ws + off); }
 
-StepArgs step_args(const Plan& p, void* ws, int batch, const float* wavelet, int64_t wstride) {
+// batch: forward batch (phase kPhaseFwd) or reverse batch (kPhaseRev)
+StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* wavelet, int64_t wstride) {
   StepArgs a{};
-  a.d = p.d;
-  a.S = p.S;
-  a.xcd_map = p.xcd_map;
-  a.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
+  const bool rev = phase == kPhaseRev;
+  a.d = rev ? p.dr : p.d;
+  a.S = rev ? p.Sr : p.S;
+  a.xcd_map = rev ? p.xcd_map_r : p.xcd_map;
+  a.slots = rev ? at<SlotInfo>(ws, p.L.rslots) + (size_t)batch * p.Sr
+                : at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
   a.shots = at<ShotDesc>(ws, p.L.shots);
   a.rdir = at<RmapDir>(ws, p.L.rdir);
   a.rrows = at<RmapRow>(ws, p.L.rrows);
@@ -395,11 +434,11 @@ StepArgs step_args(const Plan& p, void* ws, int batch, const float* wavelet, int
   return a;
 }
 
-ExtArgs ext_args(const Plan& p, void* ws, int batch) {
+ExtArgs ext_args(const Plan& p, void* ws, int rbatch) {
   ExtArgs e{};
   e.d = p.d;
-  e.S = p.S;
-  e.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
+  e.S = p.Sr;
+  e.slots = at<SlotInfo>(ws, p.L.rslots) + (size_t)rbatch * p.Sr;
   e.shots = at<ShotDesc>(ws, p.L.shots);
   e.lam = at<float>(ws, p.L.xlam);
   e.D = at<float>(ws, p.L.xD);
@@ -428,7 +467,7 @@ hipError_t get_capture_stream(hipStream_t* out) {
 int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, const float* wavelet,
               int64_t wstride, hipStream_t stream) {
   if (nsteps <= 0) return FWI_OK;
-  StepArgs a = step_args(p, ws, batch, wavelet, wstride);
+  StepArgs a = step_args(p, ws, batch, phase, wavelet, wstride);
   // reverse sweeps with kRevExt keep lam and D of the last ext_T steps and
   // fold them into the extended image after every ext_T steps
   const bool ext = phase == kPhaseRev && (flags & kRevExt);
@@ -516,6 +555,8 @@ int upload_tables(const Plan& p, void* ws, hipStream_t s) {
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.slots), p.slots.data(), sizeof(SlotInfo) * p.slots.size(),
                          hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rslots), p.rslots.data(), sizeof(SlotInfo) * p.rslots.size(),
+                         hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rdir), p.rdir.data(), sizeof(RmapDir) * p.rdir.size(),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rrows), p.rrows.data(), sizeof(RmapRow) * p.rrows.size(),
@@ -567,20 +608,23 @@ int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipSt
   return FWI_OK;
 }
 
-int reverse_batch(Plan& p, void* ws, int b, const float* wavelet, int64_t wstride, hipStream_t s,
+// rb: reverse batch
+int reverse_batch(Plan& p, void* ws, int rb, const float* wavelet, int64_t wstride, hipStream_t s,
                   int flags = 0) {
-  const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), 2 * p.d.field, 2 * p.d.field, slots, p.S, 0, s));
-  return run_steps(p, ws, b, kPhaseRev, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
+  const SlotInfo* slots = at<SlotInfo>(ws, p.L.rslots) + (size_t)rb * p.Sr;
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), 2 * p.d.field, 2 * p.d.field, slots, p.Sr, 0, s));
+  return run_steps(p, ws, rb, kPhaseRev, flags, p.rbatch_nt[rb] - 1, wavelet, wstride, s);
 }
 
-int epilogue_batch(Plan& p, void* ws, int b, const float* v, float* H1, float* D, int hmax,
+// b: reverse batch (rev, E of the reverse slots) or forward batch (E of the
+// forward-only Hessian sweep)
+int epilogue_batch(Plan& p, void* ws, int b, bool rev, const float* v, float* H1, float* D, int hmax,
                    int rcv_model, hipStream_t s) {
   if (!H1 && !D) return FWI_OK;
   EpiArgs e{};
   e.d = p.d;
-  e.S = p.S;
-  e.slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
+  e.S = rev ? p.Sr : p.S;
+  e.slots = rev ? at<SlotInfo>(ws, p.L.rslots) + (size_t)b * p.Sr : at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
   e.shots = at<ShotDesc>(ws, p.L.shots);
   e.E = at<float>(ws, p.L.E);
   e.v = v;
@@ -626,26 +670,33 @@ double time_steps(Plan& p, void* ws, int flags, int phase, int nsteps, const flo
   return ms;
 }
 
-// Chooses rows per tile and shots in flight by timing a few steps of the
-// phases the call will run; results are cached per (grid, geometry, what).
+// Chooses shots in flight, rows per tile and prefetch depth of the forward
+// and of the reverse sweep by timing a few launches of each candidate;
+// results are cached per (grid, geometry, kind of call, GPU model).
 int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, uint64_t ikey,
              void* ws, size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride,
              hipStream_t s, ExecChoice& best) {
   const int ns = geo->nshot;
   const int Smax = best.S;
-  std::vector<int> Ss, TZs, PFs;
+  std::vector<int> Ss, TZf, TZr, PFs, RFs;
   if (ex && ex->shots_in_flight > 0) Ss = {ex->shots_in_flight};
   else
     for (int c : {8, 16, 32, 64})
       if (c <= Smax) Ss.push_back(c);
   if (Ss.empty()) Ss = {Smax};
-  if (ex && ex->tile_rows > 0) TZs = {ex->tile_rows};
-  else TZs = {16, 32, 64, 128};
-  std::vector<int> RFs;
+  // the forward sweep (one field, fewer registers) likes long tiles and many
+  // shots; the reverse sweep (two fields) short tiles
+  if (ex && ex->tile_rows > 0) TZf = {ex->tile_rows};
+  else TZf = {16, 32, 64, 128};
+  if (ex && ex->tile_rows_reverse > 0) TZr = {ex->tile_rows_reverse};
+  else if (ex && ex->tile_rows > 0) TZr = {ex->tile_rows};
+  else TZr = {8, 12, 16, 32, 64};
   if (ex && ex->prefetch > 0) PFs = {ex->prefetch};
   else PFs = {1, 3, 7};
   if (ex && ex->prefetch_reverse > 0) RFs = {ex->prefetch_reverse};
   else RFs = {1, 3};
+  std::vector<int> SRs = Ss;
+  if (ex && ex->shots_in_flight_reverse > 0) SRs = {ex->shots_in_flight_reverse};
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
                      what == FWI_WS_GNHVP);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
@@ -655,37 +706,70 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     return std::min(time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s),
                     time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s));
   };
-  // forward and reverse sweeps are tuned separately for each (S, TZ); the
-  // score is the time of one forward plus one reverse step per shot.  A
-  // candidate replaces the current best only when it is 2% faster, so that
-  // near-ties resolve to the earliest candidate (fewest shots in flight,
-  // shortest tiles, shortest prefetch) from run to run.
-  double best_rate = -1.0;
-  ExecChoice choice = best;
+  struct Cand {
+    int S, TZ, pf;
+    double per_shot;  // ms per shot and step
+  };
+  std::vector<Cand> F, Rv;
+  std::vector<int> TZs = TZf;
+  for (int t : TZr)
+    if (std::find(TZs.begin(), TZs.end(), t) == TZs.end()) TZs.push_back(t);
+  std::sort(TZs.begin(), TZs.end());
   for (int S : Ss) {
     for (int TZ : TZs) {
-      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0]};
+      const bool tf = std::find(TZf.begin(), TZf.end(), TZ) != TZf.end();
+      const bool tr = grad && std::find(TZr.begin(), TZr.end(), TZ) != TZr.end() &&
+                      std::find(SRs.begin(), SRs.end(), S) != SRs.end();
+      if (!tf && !tr) continue;
+      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ};
       auto p = build_plan(g, geo, c, 0, what, 0);
       if (p->L.total > ws_bytes) continue;
       if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
       HIP_TRY(launch_fill(at<char>(ws, p->L.u), p->L.g - p->L.u, s));
-      double fbest = 1e30, rbest = grad ? 1e30 : 0.0;
-      int fpf = c.pf_fwd, rpf = c.pf_rev;
-      for (int pf : PFs) {
-        p->pf_fwd = pf;
-        const double ms = timed(*p, fwd_flags, kPhaseFwd);
-        if (ms < fbest * 0.98) { fbest = ms; fpf = pf; }
+      const double shots = std::min(S, std::max(ns, 1));
+      // within one (S, TZ) a longer prefetch must win by 2 %, so near-ties
+      // resolve to the shorter one from run to run
+      if (tf) {
+        double fb = 1e30;
+        int fpf = PFs[0];
+        for (int pf : PFs) {
+          p->pf_fwd = pf;
+          const double ms = timed(*p, fwd_flags, kPhaseFwd);
+          if (ms < fb * 0.98) { fb = ms; fpf = pf; }
+        }
+        F.push_back(Cand{S, TZ, fpf, fb / shots});
       }
-      for (int pf : (grad ? RFs : std::vector<int>{})) {
-        p->pf_rev = pf;
-        const double mr = timed(*p, 0, kPhaseRev);
-        if (mr < rbest * 0.98) { rbest = mr; rpf = pf; }
+      if (tr) {
+        double rb = 1e30;
+        int rpf = RFs[0];
+        for (int pf : RFs) {
+          p->pf_rev = pf;
+          const double ms = timed(*p, 0, kPhaseRev);
+          if (ms < rb * 0.98) { rb = ms; rpf = pf; }
+        }
+        Rv.push_back(Cand{S, TZ, rpf, rb / shots});
       }
-      const int shots = std::min(S, std::max(ns, 1));
-      const double rate = (double)shots / (fbest + rbest);
-      if (rate > best_rate * 1.02) {
-        best_rate = rate;
-        choice = ExecChoice{S, TZ, best.graph_steps, fpf, rpf};
+    }
+  }
+  if (F.empty()) return FWI_OK;  // nothing fitted the workspace: keep the defaults
+  // the pair with the least time per shot, the reverse's shots in flight
+  // dividing the forward's; a later pair must be 2 % faster to replace one
+  double best_t = 1e300;
+  ExecChoice choice = best;
+  for (const Cand& f : F) {
+    if (!grad) {
+      if (f.per_shot < best_t * 0.98) {
+        best_t = f.per_shot;
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ};
+      }
+      continue;
+    }
+    for (const Cand& r : Rv) {
+      if (r.S > f.S || f.S % r.S) continue;
+      const double t = f.per_shot + r.per_shot;
+      if (t < best_t * 0.98) {
+        best_t = t;
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ};
       }
     }
   }
@@ -707,6 +791,8 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.graph_steps = (ex && ex->graph_steps != 0) ? ex->graph_steps : 32;
   c.pf_fwd = (ex && ex->prefetch > 0) ? ex->prefetch : 3;
   c.pf_rev = (ex && ex->prefetch_reverse > 0) ? ex->prefetch_reverse : 1;
+  c.Sr = (ex && ex->shots_in_flight_reverse > 0) ? ex->shots_in_flight_reverse : 0;
+  c.TZr = (ex && ex->tile_rows_reverse > 0) ? ex->tile_rows_reverse : 0;
   return c;
 }
 
@@ -720,7 +806,9 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
   if (what == FWI_WS_BORN) what = FWI_WS_FORWARD;
   std::vector<uint64_t> k = {h.h, (uint64_t)what, (uint64_t)(ex ? ex->shots_in_flight : 0),
                              (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0),
-                             (uint64_t)(ex ? ex->prefetch_reverse : 0)};
+                             (uint64_t)(ex ? ex->prefetch_reverse : 0),
+                             (uint64_t)(ex ? ex->shots_in_flight_reverse : 0),
+                             (uint64_t)(ex ? ex->tile_rows_reverse : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -742,7 +830,7 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
 
 // Tuned choices persist across processes in a plain text file named by the
 // environment variable FWI_TUNE_CACHE: one line per key,
-//   "<key words in hex> : S TZ graph_steps prefetch prefetch_reverse".
+//   "<key words in hex> : S TZ graph_steps prefetch prefetch_reverse S_rev TZ_rev".
 std::string key_text(const std::vector<uint64_t>& k) {
   std::string out;
   char buf[24];
@@ -766,7 +854,9 @@ bool cache_lookup(const std::vector<uint64_t>& k, ExecChoice& c) {
     if (!colon) continue;
     if (std::string(line, colon - line) != want) continue;
     ExecChoice t{};
-    if (sscanf(colon + 1, "%d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev) == 5 &&
+    if (sscanf(colon + 1, "%d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
+               &t.TZr) == 7 &&
+        t.Sr > 0 && t.S % t.Sr == 0 && t.TZr >= 8 && t.TZr <= 4096 &&
         t.S > 0 && t.TZ >= 8 && t.TZ <= 4096 && (t.graph_steps == -1 || (t.graph_steps > 0 && t.graph_steps <= 1024)) &&
         (t.pf_fwd == 1 || t.pf_fwd == 3 || t.pf_fwd == 7) &&
         (t.pf_rev == 1 || t.pf_rev == 3)) {
@@ -783,25 +873,33 @@ void cache_store(const std::vector<uint64_t>& k, const ExecChoice& c) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s: %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev);
+  fprintf(f, "%s: %d %d %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev,
+          c.Sr, c.TZr);
   fclose(f);
 }
 
 // Returns the plan for a call; with autotuning requested and no cached
 // choice, runs the tuner inside `ws` first (needs a workspace sized for the
 // untuned maximum, which fwi_workspace_bytes reports).
-int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, void* ws,
-             size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride, hipStream_t s,
-             std::shared_ptr<Plan>& out, bool sizing_only, int ext_h = -1) {
-  const int plain = ex && ex->mode == FWI_EXEC_PLAIN;
+int check_exec(const fwi_exec* ex) {
   if (ex && ex->mode != FWI_EXEC_PLAIN && ex->mode != FWI_EXEC_BATCHED) return fail(FWI_ERR_ARG, "bad exec mode");
-  if (ex && (ex->shots_in_flight < 0 || ex->tile_rows < 0 || ex->graph_steps < -1))
+  if (ex && (ex->shots_in_flight < 0 || ex->tile_rows < 0 || ex->graph_steps < -1 ||
+             ex->shots_in_flight_reverse < 0 || ex->tile_rows_reverse < 0))
     return fail(FWI_ERR_ARG, "bad exec settings");
-  if (ex && ex->tile_rows > 0 && ex->tile_rows < 8) return fail(FWI_ERR_ARG, "tile_rows must be >= 8");
+  if (ex && ((ex->tile_rows > 0 && ex->tile_rows < 8) || (ex->tile_rows_reverse > 0 && ex->tile_rows_reverse < 8)))
+    return fail(FWI_ERR_ARG, "tile_rows must be >= 8");
   if (ex && ex->prefetch != 0 && ex->prefetch != 1 && ex->prefetch != 3 && ex->prefetch != 7)
     return fail(FWI_ERR_ARG, "prefetch must be 0, 1, 3 or 7");
   if (ex && ex->prefetch_reverse != 0 && ex->prefetch_reverse != 1 && ex->prefetch_reverse != 3)
     return fail(FWI_ERR_ARG, "prefetch_reverse must be 0, 1 or 3");
+  return FWI_OK;
+}
+
+int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int what, void* ws,
+             size_t ws_bytes, const float* v, const float* wavelet, int64_t wstride, hipStream_t s,
+             std::shared_ptr<Plan>& out, bool sizing_only, int ext_h = -1) {
+  const int plain = ex && ex->mode == FWI_EXEC_PLAIN;
+  if (int rc = check_exec(ex)) return rc;
   ExecChoice c = base_choice(g, geo, ex);
   const bool tune = !plain && ex && ex->autotune && !sizing_only;
   const uint64_t ikey = inputs_hash(g, geo);
@@ -810,6 +908,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     // the workspace is sized for the largest candidate
     if (!(ex->shots_in_flight > 0)) c.S = std::min(std::max(geo->nshot, 1), 64);
     if (!(ex->tile_rows > 0)) c.TZ = 32;
+    c.Sr = 0;  // reverse buffers sized for the forward's maximum
   }
   if (tune) {
     const auto tk = tune_key(g, geo, ex, what);
@@ -817,7 +916,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     ExecChoice t = c;
     if (it != g_tuned.end()) {
       c = it->second;
-    } else if (cache_lookup(tk, t) && t.S <= c.S) {
+    } else if (cache_lookup(tk, t) && t.S <= c.S && t.Sr <= c.S) {
       g_tuned[tk] = t;
       c = t;
     } else {
@@ -838,6 +937,8 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.graph_steps);
   h.pod(c.pf_fwd);
   h.pod(c.pf_rev);
+  h.pod(c.Sr);
+  h.pod(c.TZr);
   h.pod(ext_h);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
@@ -896,6 +997,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   int rc = check_inputs(grid, geom);
   if (rc) return rc;
   if (!chosen) return fail(FWI_ERR_ARG, "chosen must not be NULL");
+  if ((rc = check_exec(exec))) return rc;
   if (what < FWI_WS_FORWARD || what > FWI_WS_GNHVP || what == FWI_WS_PRECOND)
     return fail(FWI_ERR_ARG, "bad `what`");
   const int plain = exec && exec->mode == FWI_EXEC_PLAIN;
@@ -907,7 +1009,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
     ExecChoice t{};
     if (it != g_tuned.end()) {
       c = it->second;
-    } else if (cache_lookup(tk, t) && t.S <= c.S) {
+    } else if (cache_lookup(tk, t) && t.S <= c.S && t.Sr <= c.S) {
       c = t;
     }
   }
@@ -918,6 +1020,14 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   chosen->graph_steps = plain ? -1 : c.graph_steps;
   chosen->prefetch = c.pf_fwd;
   chosen->prefetch_reverse = c.pf_rev;
+  {
+    // the reverse sweep's settings as build_plan resolves them
+    const int S = chosen->shots_in_flight;
+    int Sr = (plain || c.Sr <= 0) ? S : std::max(1, std::min(c.Sr, S));
+    if (S % Sr) Sr = S;
+    chosen->shots_in_flight_reverse = Sr;
+    chosen->tile_rows_reverse = c.TZr > 0 ? c.TZr : c.TZ;
+  }
   return FWI_OK;
 }
 
@@ -1076,7 +1186,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
     }
   }
   if (part != 1) {
-    HIP_TRY(launch_fill(at<float>(ws, cp.L.g), model_bytes * cp.S, s));
+    HIP_TRY(launch_fill(at<float>(ws, cp.L.g), model_bytes * cp.Sr, s));
     if (illum) HIP_TRY(launch_fill(illum, model_bytes, s));
     if (offset_diag) HIP_TRY(launch_fill(offset_diag, model_bytes * (2 * hmax + 1), s));
     if (ext) HIP_TRY(launch_fill(at<float>(ws, cp.L.xI), model_bytes * (2 * ext_h + 1), s));
@@ -1088,15 +1198,17 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
       if ((rc = misfit_batch(*p, ws, b, gn ? nullptr : d_obs, misfit, s))) return rc;
     }
     if (part == 0) {
-      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s, (ext ? kRevExt : 0) | (eq3 ? kRevImgU : 0))))
-        return rc;
-      if ((rc = epilogue_batch(*p, ws, b, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
+      for (int rb = cp.rbatch_begin[b]; rb < cp.rbatch_begin[b + 1]; ++rb) {
+        if ((rc = reverse_batch(*p, ws, rb, wavelet, wstride, s, (ext ? kRevExt : 0) | (eq3 ? kRevImgU : 0))))
+          return rc;
+        if ((rc = epilogue_batch(*p, ws, rb, true, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
+      }
     }
   }
   if (part == 2) {
-    for (int b = 0; b < cp.nbatch; ++b) {
-      if ((rc = reverse_batch(*p, ws, b, wavelet, wstride, s))) return rc;
-      if ((rc = epilogue_batch(*p, ws, b, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
+    for (int rb = 0; rb < cp.nrbatch; ++rb) {
+      if ((rc = reverse_batch(*p, ws, rb, wavelet, wstride, s))) return rc;
+      if ((rc = epilogue_batch(*p, ws, rb, true, v, illum, offset_diag, hmax, rcv_model, s))) return rc;
     }
   }
   if (part != 2) {
@@ -1108,7 +1220,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
   }
   if (part != 1 && grad) {
     // eq. (3) literally: g3 = -(2/v^3) dt^2 sum lam_r[m] u[m-1]
-    HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.S, v, grad_scale, eq3 ? -cp.dt * cp.dt : 1.0, grad,
+    HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.Sr, v, grad_scale, eq3 ? -cp.dt * cp.dt : 1.0, grad,
                                 &hd->err, s));
   }
   if (ext) HIP_TRY(launch_ext_out(cp.d, at<float>(ws, cp.L.xI), ext_h, v, image, &hd->err, s));
@@ -1188,7 +1300,7 @@ int fwi_hessian_diag(const fwi_grid* grid, const fwi_geometry* geom, const fwi_e
   if ((rc = begin_call(*p, workspace, v, s))) return rc;
   for (int b = 0; b < p->nbatch; ++b) {
     if ((rc = forward_batch(*p, workspace, b, kFwdIllum, wavelet, wavelet_stride, s))) return rc;
-    if ((rc = epilogue_batch(*p, workspace, b, v, H1, D, hmax, rcv_model, s))) return rc;
+    if ((rc = epilogue_batch(*p, workspace, b, false, v, H1, D, hmax, rcv_model, s))) return rc;
   }
   return FWI_OK;
 }

@@ -155,3 +155,23 @@ def test_eq3_literal_is_gradient_only(lib):
     with pytest.raises(B.FwiError) as e:
         B.fwi_extended_image(g, geo, None, fake, fake, 0, fake, "eq3", fake, None, 4, fake, fake, 1 << 40, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
+
+
+def test_reverse_launch_settings(lib):
+    """The reverse sweep's shots in flight must divide the forward's, else the
+    forward's value is used; its tile rows default to the forward's."""
+    w = layered_1024x384(nshot=8)
+    q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=8, shots_in_flight_reverse=4,
+                                                     tile_rows=32, tile_rows_reverse=12), B.WS_GRADIENT)
+    assert (q["shots_in_flight"], q["shots_in_flight_reverse"], q["tile_rows"], q["tile_rows_reverse"]) == \
+        (8, 4, 32, 12)
+    q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=8, shots_in_flight_reverse=3), B.WS_GRADIENT)
+    assert q["shots_in_flight_reverse"] == 8
+    q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=8, tile_rows=16), B.WS_GRADIENT)
+    assert q["tile_rows_reverse"] == 16
+    g, geo = _tiny()
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_exec_query(g, geo, B.make_exec(tile_rows_reverse=4), B.WS_GRADIENT)
+    a = B.fwi_workspace_bytes(g, geo, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=1), B.WS_GRADIENT)
+    b = B.fwi_workspace_bytes(g, geo, B.make_exec(shots_in_flight=2), B.WS_GRADIENT)
+    assert 0 < a < b                      # adjoint fields for one reverse slot instead of two

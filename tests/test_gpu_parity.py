@@ -26,6 +26,9 @@ EXECS = {
     "plain": B.make_exec(mode=B.EXEC_PLAIN),
     "batched_direct": B.make_exec(shots_in_flight=2, graph_steps=-1, tile_rows=16),
     "batched_graph": B.make_exec(shots_in_flight=3, graph_steps=7, tile_rows=24),
+    # the reverse sweep takes each forward batch two shots at a time, 8-row tiles
+    "split_config": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=16, tile_rows_reverse=8,
+                                graph_steps=5),
 }
 
 
