@@ -102,8 +102,9 @@ struct ExtArgs {
   const float* lam;     // [slot][T][model]
   const float* D;       // [slot][T][model]
   int32_t T;
-  float* I;             // [2 hmax + 1][model]
+  float* I;             // [groups][2 hmax + 1][model]: one partial sum per slot group
   int32_t hmax;
+  int32_t groups;       // slots are split into this many groups (parallelism)
   const int32_t* step_ctr;
   int32_t step0, count;
   const int32_t* err;
@@ -156,7 +157,7 @@ hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_
 // flags: 0, kRevExt (StepArgs::ext_* set) or kRevImgU
 hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s);
 hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
-hipError_t launch_ext_out(const Dims& d, const float* Iacc, int hmax, const float* v, float* image,
+hipError_t launch_ext_out(const Dims& d, const float* Iacc, int groups, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);
 hipError_t launch_set(int32_t* ctr, int32_t value, hipStream_t s);

@@ -628,13 +628,110 @@ __global__ __launch_bounds__(256) void k_ext_image(ExtArgs a) {
     if (h >= -H && h <= H) a.I[(int64_t)(h + H) * d.model + cell] += acc[h + HM];
 }
 
-// image(x, h) = (2 / v(x)^3) Iacc(x, h)
-__global__ void k_ext_out(Dims d, const float* Iacc, int nh, const float* v, float* image, const int32_t* err) {
+// Four columns per lane: each lane keeps the 2HM+1 sums of 4 adjacent
+// columns, reads its 4 + 2HM operands of lam and D per step as float4 rows
+// from LDS (one read per operand serves up to four products instead of one),
+// and the next step's rows are loaded while the current one is folded.  The
+// slots are split into `groups` so that enough wavefronts run; each group
+// adds into its own partial image.
+template <int HM>
+__global__ __launch_bounds__(256) void k_ext_image4(ExtArgs a) {
+  constexpr int C = 4;
+  constexpr int TW = kWave * C;           // columns per wavefront
+  constexpr int L = TW + 2 * HM;          // staged row length
+  constexpr int NL = (L + kWave - 1) / kWave;
+  constexpr int WIN = C + 2 * HM;         // operands one lane reads
+  static_assert(HM % 4 == 0, "window reads are float4");
+  __shared__ __align__(16) float shL_all[kWavesPerBlock][L];
+  __shared__ __align__(16) float shD_all[kWavesPerBlock][L];
+  const Dims& d = a.d;
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  const int XTw = (d.nx + TW - 1) / TW;
+  const int per_group = d.nz * XTw;
+  const int wave = blockIdx.x * kWavesPerBlock + wv;
+  if (wave >= per_group * a.groups || *a.err) return;
+  const int grp = wave / per_group, rem = wave % per_group;
+  const int iz = rem / XTw, x0 = (rem % XTw) * TW;
+  const int spg = (a.S + a.groups - 1) / a.groups;
+  const int s_lo = grp * spg, s_hi = min(a.S, s_lo + spg);
+  const int H = a.hmax;
+  const int j0 = (a.step_ctr ? *a.step_ctr : 0) + a.step0;
+  const int n_it = max(s_hi - s_lo, 0) * a.count;
+  float* shL = shL_all[wv];
+  float* shD = shD_all[wv];
+  float acc[C][2 * HM + 1];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int h = 0; h < 2 * HM + 1; ++h) acc[c][h] = 0.0f;
+  float nl[NL], nd[NL];
+  // loads of iteration `it` = (slot s_lo + it / count, step it % count); a
+  // slot whose shot has ended contributes zeros
+  auto issue = [&](int it) {
+    const int s = s_lo + it / a.count, j = j0 + it % a.count;
+    const SlotInfo si = a.slots[s];
+    const bool ok = si.shot >= 0 && a.shots[si.shot].nt - 1 - j >= 1;
+    const int64_t row = ((int64_t)s * a.T + j % a.T) * d.model + (int64_t)iz * d.nx;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int c = lane + kWave * q;
+      const int xx = x0 - HM + c;
+      const bool in = ok && c < L && xx >= 0 && xx < d.nx;
+      nl[q] = in ? a.lam[row + xx] : 0.0f;
+      nd[q] = in ? a.D[row + xx] : 0.0f;
+    }
+  };
+  if (n_it > 0) issue(0);
+  for (int it = 0; it < n_it; ++it) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int c = lane + kWave * q;
+      if (c < L) {
+        shL[c] = nl[q];
+        shD[c] = nd[q];
+      }
+    }
+    if (it + 1 < n_it) issue(it + 1);
+    wave_lds_fence();
+    float lw[WIN], dw[WIN];
+#pragma unroll
+    for (int k = 0; k < WIN / 4; ++k) {
+      const float4 tl = *reinterpret_cast<const float4*>(shL + C * lane + 4 * k);
+      const float4 td = *reinterpret_cast<const float4*>(shD + C * lane + 4 * k);
+      lw[4 * k] = tl.x; lw[4 * k + 1] = tl.y; lw[4 * k + 2] = tl.z; lw[4 * k + 3] = tl.w;
+      dw[4 * k] = td.x; dw[4 * k + 1] = td.y; dw[4 * k + 2] = td.z; dw[4 * k + 3] = td.w;
+    }
+    // column x0 + C lane + c, offset h: lam at window index c + HM - h, D at c + HM + h
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int h = -HM; h <= HM; ++h)
+        if (h >= -H && h <= H) acc[c][h + HM] = fmaf(lw[c + HM - h], dw[c + HM + h], acc[c][h + HM]);
+    wave_lds_fence();
+  }
+  float* I = a.I + (int64_t)grp * (2 * H + 1) * d.model;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int x = x0 + C * lane + c;
+    if (x >= d.nx) continue;
+    const int64_t cell = (int64_t)iz * d.nx + x;
+#pragma unroll
+    for (int h = -HM; h <= HM; ++h)
+      if (h >= -H && h <= H) I[(int64_t)(h + H) * d.model + cell] += acc[c][h + HM];
+  }
+}
+
+// image(x, h) = (2 / v(x)^3) sum over groups of Iacc[g](x, h), fixed order
+__global__ void k_ext_out(Dims d, const float* Iacc, int groups, int nh, const float* v, float* image,
+                          const int32_t* err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.model * nh) return;
   const int64_t cell = i % d.model;
+  double sum = 0.0;
+  for (int g = 0; g < groups; ++g) sum += (double)Iacc[(int64_t)g * nh * d.model + i];
   const double vv = v[cell];
-  image[i] = (*err) ? NAN : (float)(2.0 / (vv * vv * vv) * (double)Iacc[i]);
+  image[i] = (*err) ? NAN : (float)(2.0 / (vv * vv * vv) * sum);
 }
 
 // -------------------------------------------------------------------------
@@ -955,19 +1052,27 @@ hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_
 hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s) {
   const int XTm = (a.d.nx + kWave - 1) / kWave;
   const dim3 grid(blocks_for((int64_t)a.d.nz * XTm, kWavesPerBlock)), block(256);
-  if (a.hmax < 0 || a.T < 1 || a.count < 1) return hipErrorInvalidValue;
-  if (a.hmax <= 4) hipLaunchKernelGGL(k_ext_image<4>, grid, block, 0, s, a);
-  else if (a.hmax <= 8) hipLaunchKernelGGL(k_ext_image<8>, grid, block, 0, s, a);
-  else if (a.hmax <= 16) hipLaunchKernelGGL(k_ext_image<16>, grid, block, 0, s, a);
-  else if (a.hmax <= 32) hipLaunchKernelGGL(k_ext_image<32>, grid, block, 0, s, a);
-  else return hipErrorInvalidValue;
+  if (a.hmax < 0 || a.T < 1 || a.count < 1 || a.groups < 1) return hipErrorInvalidValue;
+  if (a.hmax <= 16) {
+    const int XTw = (a.d.nx + 4 * kWave - 1) / (4 * kWave);
+    const dim3 g4(blocks_for((int64_t)a.d.nz * XTw * a.groups, kWavesPerBlock));
+    if (a.hmax <= 4) hipLaunchKernelGGL(k_ext_image4<4>, g4, block, 0, s, a);
+    else if (a.hmax <= 8) hipLaunchKernelGGL(k_ext_image4<8>, g4, block, 0, s, a);
+    else hipLaunchKernelGGL(k_ext_image4<16>, g4, block, 0, s, a);
+  } else if (a.hmax <= 32) {
+    if (a.groups != 1) return hipErrorInvalidValue;  // one wavefront per column tile takes every slot
+    hipLaunchKernelGGL(k_ext_image<32>, grid, block, 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_ext_out(const Dims& d, const float* Iacc, int hmax, const float* v, float* image,
+hipError_t launch_ext_out(const Dims& d, const float* Iacc, int groups, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s) {
   const int nh = 2 * hmax + 1;
-  hipLaunchKernelGGL(k_ext_out, dim3(blocks_for(d.model * nh, 256)), dim3(256), 0, s, d, Iacc, nh, v, image, err);
+  hipLaunchKernelGGL(k_ext_out, dim3(blocks_for(d.model * nh, 256)), dim3(256), 0, s, d, Iacc, groups, nh, v,
+                     image, err);
   return hipGetLastError();
 }
 

@@ -146,6 +146,7 @@ struct Plan {
   int split = 0, plain = 0, graph_steps = 0, xcd_map = 0, what = 0;
   int pf_fwd = 3, pf_rev = 1;  // prefetch distances of the forward / reverse sweeps
   int ext_h = -1, ext_T = 0;   // extended imaging: offset bound (-1: off), ring of reverse steps
+  int ext_groups = 1;          // partial images (slot groups) of the extended image
   int born = 0;                // Born perturbation wavefield buffers present
   double sp_a = 0.0;
   double dx = 0, dt = 0;
@@ -386,7 +387,9 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.strip = grad ? take(sizeof(float) * p->strip_stride * p->ncs) : o;
   L.xlam = ext ? take(sizeof(float) * d.model * p->ext_T * p->Sr) : o;
   L.xD = ext ? take(sizeof(float) * d.model * p->ext_T * p->Sr) : o;
-  L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1)) : o;
+  // up to 4 slot groups fold in parallel for |h| <= 16 (one for larger offsets)
+  p->ext_groups = ext ? (p->ext_h <= 16 ? std::min(p->Sr, 4) : 1) : 1;
+  L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1) * p->ext_groups) : o;
   L.bu = p->born ? take(sizeof(float) * kULevels * d.field * p->ncs) : o;
   L.bw = p->born ? take(sizeof(float) * d.field) : o;
   L.total = o;
@@ -445,6 +448,7 @@ ExtArgs ext_args(const Plan& p, void* ws, int rbatch) {
   e.T = p.ext_T;
   e.I = at<float>(ws, p.L.xI);
   e.hmax = p.ext_h;
+  e.groups = p.ext_groups;
   e.step_ctr = nullptr;
   e.step0 = 0;
   e.count = 0;
@@ -1189,7 +1193,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
     HIP_TRY(launch_fill(at<float>(ws, cp.L.g), model_bytes * cp.Sr, s));
     if (illum) HIP_TRY(launch_fill(illum, model_bytes, s));
     if (offset_diag) HIP_TRY(launch_fill(offset_diag, model_bytes * (2 * hmax + 1), s));
-    if (ext) HIP_TRY(launch_fill(at<float>(ws, cp.L.xI), model_bytes * (2 * ext_h + 1), s));
+    if (ext) HIP_TRY(launch_fill(at<float>(ws, cp.L.xI), model_bytes * (2 * ext_h + 1) * cp.ext_groups, s));
   }
   for (int b = 0; b < cp.nbatch; ++b) {
     if (part != 2) {
@@ -1223,7 +1227,7 @@ static int gradient_impl(const fwi_grid* grid, const fwi_geometry* geom, const f
     HIP_TRY(launch_gradient_out(cp.d, at<float>(ws, cp.L.g), cp.Sr, v, grad_scale, eq3 ? -cp.dt * cp.dt : 1.0, grad,
                                 &hd->err, s));
   }
-  if (ext) HIP_TRY(launch_ext_out(cp.d, at<float>(ws, cp.L.xI), ext_h, v, image, &hd->err, s));
+  if (ext) HIP_TRY(launch_ext_out(cp.d, at<float>(ws, cp.L.xI), cp.ext_groups, ext_h, v, image, &hd->err, s));
   if (part == 1) {
     std::lock_guard<std::mutex> lock(g_mutex);
     p->fwd_ws = ws;
