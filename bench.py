@@ -106,7 +106,7 @@ def measured_traffic(kname, chosen):
     if p.get("kernel_source_sha") != kernel_hash():
         return None
     keys = ("shots_in_flight", "tile_rows", "graph_steps", "prefetch", "prefetch_reverse",
-            "shots_in_flight_reverse", "tile_rows_reverse")
+            "shots_in_flight_reverse", "tile_rows_reverse", "reverse_steps")
     if any(p["launch_config"].get(k) != chosen.get(k) for k in keys):
         return None
     return p.get("bytes_per_launch")
@@ -240,9 +240,9 @@ def main():
     if args.exec:
         vals = [int(x) for x in args.exec.split(",")]
         S_, TZ_, G_, PF_, PR_ = vals[:5]
-        SR_, TZR_ = (vals[5:7] + [0, 0])[:2] if len(vals) > 5 else (0, 0)
+        SR_, TZR_, RS_ = (vals[5:8] + [0, 0, 0])[:3]
         ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_,
-                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_)
+                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_, reverse_steps=RS_)
     else:
         ex = B.make_exec(autotune=1)
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
@@ -304,7 +304,8 @@ def main():
     S = max(1, chosen["shots_in_flight"])
     Sr = max(1, chosen["shots_in_flight_reverse"])
     order = sorted(range(shots), key=lambda s: -int(nt[s]))
-    launches = sum(int(nt[order[b + j]]) - 1 for b in range(0, shots, S) for j in range(0, S, Sr)
+    RS = max(1, chosen["reverse_steps"])
+    launches = sum((int(nt[order[b + j]]) - 1 + RS - 1) // RS for b in range(0, shots, S) for j in range(0, S, Sr)
                    if b + j < shots)
     launch_us = rev_ms * 1e3 / max(launches, 1)
     bytes_per_launch = rev_bytes / max(launches, 1)
@@ -336,7 +337,8 @@ def main():
                    "graph_steps": chosen["graph_steps"], "prefetch": chosen["prefetch"],
                    "prefetch_reverse": chosen["prefetch_reverse"],
                    "shots_in_flight_reverse": chosen["shots_in_flight_reverse"],
-                   "tile_rows_reverse": chosen["tile_rows_reverse"]},
+                   "tile_rows_reverse": chosen["tile_rows_reverse"],
+                   "reverse_steps": chosen["reverse_steps"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},

@@ -129,6 +129,14 @@ typedef struct {
                                  0 = tuned, or the forward's                   */
     int32_t tile_rows_reverse; /* rows per tile of the reverse sweep; 0 =
                                  tuned, or tile_rows                           */
+    int32_t reverse_steps;    /* time steps per launch of the adjoint sweep of
+                                 fwi_gradient / fwi_misfit_backward /
+                                 fwi_gn_hvp: 1, or 2 (temporal blocking: the
+                                 first step on 64 columns, the second on the 56
+                                 inside, one read and one write of every field
+                                 for both); 0 = tuned, else 1.  Two steps are
+                                 not used with a free surface, in plain mode or
+                                 for the extended image / eq. (3) variants     */
 } fwi_exec;
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
@@ -158,7 +166,8 @@ size_t fwi_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
                            const fwi_exec *exec, int what, int hmax);
 
 /* The execution settings (shots_in_flight, tile_rows, graph_steps, prefetch,
- * prefetch_reverse, shots_in_flight_reverse, tile_rows_reverse) that a
+ * prefetch_reverse, shots_in_flight_reverse, tile_rows_reverse,
+ * reverse_steps) that a
  * call with these arguments uses: the autotuned choice once tuning has run on
  * the current device, else the heuristic defaults.  Fills *chosen (mode and
  * autotune copied from exec).  Returns 0 or FWI_ERR_*. */

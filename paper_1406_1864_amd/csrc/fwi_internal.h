@@ -17,8 +17,16 @@ constexpr int kWave = 64;         // CDNA wavefront width == tile width in x
 constexpr int kWavesPerBlock = 4;  // independent wavefronts per workgroup
 constexpr int kRadius = 4;         // stencil half-width (8th order)
 // levels per checkpoint set of the source wavefield: u (two time levels) and
-// the forward sweep's increment d[n] = u[n] - u[n-1]
+// the forward sweep's increment d[n] = u[n] - u[n-1]; the two-step reverse
+// sweep adds a second pair of u levels (it reads one pair and writes the
+// other), and likewise a second pair of adjoint levels
 constexpr int kULevels = 3;
+constexpr int kULevels2 = 5;
+constexpr int kLamLevels = 2;
+constexpr int kLamLevels2 = 4;
+// output columns of a two-step reverse tile: the wavefront computes the first
+// step on 64 columns and the second on the 56 inside them
+constexpr int kTile2 = kWave - 2 * kRadius;
 
 struct Dims {
   int32_t nz, nx, N;     // model rows / columns, sponge width
@@ -44,7 +52,7 @@ struct ShotDesc {
   int32_t rdir;        // first receiver-map directory entry (one per x tile)
   int32_t rec_z0;      // shallowest receiver row (model rows)
   float xmin_m, xmax_m;  // receiver aperture in metres
-  int32_t pad_;
+  int32_t rdir2;       // first directory entry of the two-step reverse tiling
 };
 
 struct SlotInfo {
@@ -62,12 +70,14 @@ struct StepArgs {
   int32_t xcd_map;      // 1: keep each slot's tiles on one XCD
   const SlotInfo* slots;
   const ShotDesc* shots;
-  const RmapDir* rdir;
-  const RmapRow* rrows;
+  const RmapDir* rdir;   // receiver maps of the launch's tiling (the two-step
+  const RmapRow* rrows;  // reverse sweep has tiles of its own)
   const int32_t* rmaps;
   const float* w;       // dt^2 v^2 / h^2 on the padded grid (storage layout)
-  float* u;             // [cs][3][field]   u[n] at level n & 1, increment at level 2
-  float* lam;           // [slot][2][field] adjoint wavefield
+  float* u;             // [cs][ulevels][field]: u[n] at level n & 1, increment at 2
+  float* lam;           // [slot][lamlevels][field] adjoint wavefield
+  int64_t ustride;      // floats per checkpoint set of u (ulevels * field)
+  int64_t lstride;      // floats per slot of lam (lamlevels * field)
   float* g;             // [slot][model]    sum_m lam[m] D[m]
   float* E;             // [slot][model]    sum_m D[m]^2
   float* traces;        // [nt_max][ntrace] recorded u (forward) / psi' (adjoint)
@@ -157,6 +167,10 @@ hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_
 // flags: 0, kRevExt (StepArgs::ext_* set) or kRevImgU
 hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_t s);
 hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
+// two reverse steps per launch (StepArgs::d.XT = two-step tiles, receiver
+// maps of that tiling, step = launch index); no extended image, eq. (3) or
+// free surface
+hipError_t launch_reverse2(const StepArgs& a, hipStream_t s);
 hipError_t launch_ext_out(const Dims& d, const float* Iacc, int groups, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);

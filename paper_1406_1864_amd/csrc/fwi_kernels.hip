@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   const int xs0 = xt * kWave;
   const Col col = make_col(d, xs0, lane);
   const int z0 = (FS ? d.ztop : 0) + zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
-  float* ubase = a.u + (int64_t)si.cs * kULevels * d.field;
+  float* ubase = a.u + (int64_t)si.cs * a.ustride;
   const float* ucur = ubase + (int64_t)(n & 1) * d.field;
   float* unxt = ubase + (int64_t)((n + 1) & 1) * d.field;
   float* dinc = ubase + (int64_t)2 * d.field;
@@ -420,10 +420,10 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const int hmx = col.hcol - d.mx0;
   const bool hmcol = hmx >= 0 && hmx < d.nx;
   const int z0 = (FS ? d.ztop : 0) + zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);
-  float* ubase = a.u + (int64_t)si.cs * kULevels * d.field;
+  float* ubase = a.u + (int64_t)si.cs * a.ustride;
   float* u_m = ubase + (int64_t)(m & 1) * d.field;  // u[m] in, u[m-2] out
   const float* u_m1 = ubase + (int64_t)((m - 1) & 1) * d.field;
-  float* lbase = a.lam + (int64_t)slot * 2 * d.field;
+  float* lbase = a.lam + (int64_t)slot * a.lstride;
   const float* l_p1 = lbase + (int64_t)((m + 1) & 1) * d.field;  // lam[m+1]
   float* l_p2 = lbase + (int64_t)(m & 1) * d.field;              // lam[m+2] in, lam[m] out
 
@@ -567,6 +567,267 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
           if (ri >= 0) u_m[idx] = strip ? strip[ri] : 0.0f;
         }
       }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// Two reverse steps per launch, A = step m and B = step m-1 (temporal
+// blocking: the four field levels are read once and written once for two
+// steps, and g, E are updated once).  A wavefront computes step A on 64
+// columns and step B on the 56 inside them (lanes 4..59 own the output), so
+// B's horizontal neighbours are A's own results, exchanged through the
+// wavefront's LDS row; along z, A runs 4 rows ahead of B and over 4 more
+// rows on either side of the tile.  A's results of the last 10 rows stay in
+// registers for B's vertical stencil.  The sweep reads one pair of u and lam
+// levels and writes the other pair (alternating from launch to launch),
+// because neighbouring tiles read the inputs in their overlap.  Snapshot
+// restarts fall on A (even snapshot spacing), so B restarts from A's
+// registers.  Launch q runs A at m = nt-1-2q; B is skipped when m = 1.
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reverse2(StepArgs a) {
+  constexpr int PF = 1;
+  constexpr int W = 9 + PF;  // rows of the stencil rings
+  constexpr int R = PF + 1;  // rows of the point-wise rings
+  constexpr int W5 = 5;      // rows between A and B, plus one
+  constexpr int LR = kWave + 2 * kRadius;
+  static_assert(W % R == 0 && W % W5 == 0, "ring lengths must divide the unrolled period");
+  __shared__ float ldsU_all[kWavesPerBlock][LR];
+  __shared__ float ldsL_all[kWavesPerBlock][LR];
+  // A's results u[m-2], lam[m] of the last W rows: B's stencil operands
+  __shared__ float ringU_all[kWavesPerBlock][W][LR];
+  __shared__ float ringL_all[kWavesPerBlock][W][LR];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  int slot, tile;
+  if (!map_tile(a.d, a.S, a.xcd_map, wv, slot, tile)) return;
+  if (*a.err) return;
+  const SlotInfo si = a.slots[slot];
+  if (si.shot < 0) return;
+  const ShotDesc sd = a.shots[si.shot];
+  const int q = step_of(a);
+  const int m = sd.nt - 1 - 2 * q;  // step A
+  if (m < 1) return;
+  const bool hasB = m >= 2;
+
+  const Dims& d = a.d;
+  float* ldsU = ldsU_all[wv];
+  float* ldsL = ldsL_all[wv];
+  float (*ringU)[LR] = ringU_all[wv];
+  float (*ringL)[LR] = ringL_all[wv];
+  const int xt = tile % d.XT, zt = tile / d.XT;
+  // lane 0's storage column: the owned lanes 4..59 of tile xt start at padded column 56 xt
+  const int xs0 = d.off - kRadius + kTile2 * xt;
+  const Col col = make_col(d, xs0, lane);
+  const bool own_col = lane >= kRadius && lane < kWave - kRadius && col.xin;
+  const int hmx = col.hcol - d.mx0;
+  const bool hmcol = hmx >= 0 && hmx < d.nx;
+  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);  // B's (owned) rows
+  const int za0 = z0 - kRadius, za1 = z1 + kRadius;    // A's rows
+
+  // level pairs: launches with even q read the pair the forward sweep left
+  // (u[k] at level k & 1) and write levels 3, 4; odd q the other way round
+  const bool even = (q & 1) == 0;
+  float* ubase = a.u + (int64_t)si.cs * a.ustride;
+  const float* uA0 = ubase + (int64_t)(even ? (m & 1) : 3) * d.field;        // u[m]
+  const float* uA1 = ubase + (int64_t)(even ? ((m - 1) & 1) : 4) * d.field;  // u[m-1]
+  float* uO0 = ubase + (int64_t)(even ? 3 : (m & 1)) * d.field;              // u[m-2]
+  float* uO1 = ubase + (int64_t)(even ? 4 : ((m - 1) & 1)) * d.field;        // u[m-3]
+  float* lbase = a.lam + (int64_t)slot * a.lstride;
+  const float* lA1 = lbase + (int64_t)(even ? ((m + 1) & 1) : 3) * d.field;  // lam[m+1]
+  const float* lA2 = lbase + (int64_t)(even ? (m & 1) : 2) * d.field;        // lam[m+2]
+  float* lO0 = lbase + (int64_t)(even ? 2 : (m & 1)) * d.field;              // lam[m]
+  float* lO1 = lbase + (int64_t)(even ? 3 : ((m + 1) & 1)) * d.field;        // lam[m-1]
+
+  const int rem = sd.nt - 1 - m;
+  const bool reset = rem > 0 && (rem % sd.K) == 0 && rem / sd.K <= sd.nsnap;
+  const float* ckpt = a.snap + (int64_t)si.cs * a.snap_stride;
+  const float* snap0 = reset ? ckpt + (int64_t)(rem / sd.K - 1) * 2 * d.model : nullptr;
+  const float* snap1 = reset ? snap0 + d.model : nullptr;
+  const float* strip_base = a.strip + (int64_t)si.cs * a.strip_stride;
+  const float* stripA = (m >= 3) ? strip_base + (int64_t)(m - 2) * d.ring : nullptr;
+  const float* stripB = (m >= 4) ? strip_base + (int64_t)(m - 3) * d.ring : nullptr;
+  const bool first = (m == sd.nt - 1);
+  float* G = a.g + (int64_t)slot * d.model;
+  float* E = a.E + (int64_t)slot * d.model;
+
+  const bool src_tile = sd.src_z >= za0 && sd.src_z < za1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
+  const float fA = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 1)] : 0.0f;
+  const float fB = (src_tile && hasB) ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 2)] : 0.0f;
+
+  // receiver rows of this tile, one cursor for each step
+  int rpA, rpB, rend;
+  {
+    const RmapDir dir = a.rdir[sd.rdir2 + xt];
+    rpA = dir.begin;
+    rend = dir.begin + dir.count;
+    while (rpA < rend && a.rrows[rpA].z < za0) ++rpA;
+    rpB = rpA;
+    while (rpB < rend && a.rrows[rpB].z < z0) ++rpB;
+  }
+  int rzA = rpA < rend ? a.rrows[rpA].z : INT_MAX;
+  int rzB = rpB < rend ? a.rrows[rpB].z : INT_MAX;
+  const float* psiA = a.traces + (int64_t)m * a.ntrace;
+  const float* psiB = a.traces + (int64_t)(m - 1) * a.ntrace;
+
+  const int uz_lo = d.N - kRadius, uz_hi = d.N + d.nz + kRadius;  // rows where u is defined
+  // A's inputs: u[m-1], lam[m+1] (stencil rings), their halo columns and u[m],
+  // lam[m+2], w (point-wise rings); B's per-row values in 5-row rings: w,
+  // A's g and E terms, the old g and E of owned rows
+  float uc[W], lc[W];
+  float uh[R], lh[R], p0[R], pl[R], pw[R];
+  float wr[W5], cg[W5], ce[W5], go[W5], eo[W5];
+  auto load_centre = [&](int r, float& cu, float& cl) {
+    cu = cl = 0.0f;
+    if (r >= 0 && r < d.Z && col.xin) {
+      const int64_t ro = (int64_t)r * d.P;
+      cl = lA1[ro + col.xs];
+      if (r >= uz_lo && r < uz_hi) {
+        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
+        cu = (mrow && col.mcol) ? snap1[(int64_t)(r - d.N) * d.nx + col.mx] : uA1[ro + col.xs];
+      }
+    }
+  };
+  auto load_pt = [&](int r, float& hu, float& hl, float& u0, float& l2, float& w) {
+    hu = hl = u0 = l2 = w = 0.0f;
+    if (r < 0 || r >= d.Z) return;
+    const int64_t ro = (int64_t)r * d.P;
+    if (col.hok) {
+      hl = lA1[ro + col.hcol];
+      if (r >= uz_lo && r < uz_hi) {
+        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
+        hu = (mrow && hmcol) ? snap1[(int64_t)(r - d.N) * d.nx + hmx] : uA1[ro + col.hcol];
+      }
+    }
+    if (!col.xin) return;
+    const int64_t idx = ro + col.xs;
+    l2 = lA2[idx];
+    w = a.w[idx];
+    const int mz = r - d.N;
+    if (mz >= 0 && mz < d.nz && col.mcol)
+      u0 = reset ? snap0[(int64_t)mz * d.nx + col.mx] : uA0[idx];
+  };
+#pragma unroll
+  for (int j = 0; j < 8 + PF; ++j) load_centre(za0 - kRadius + j, uc[j], lc[j]);
+  load_pt(za0, uh[0], lh[0], p0[0], pl[0], pw[0]);
+
+  for (int zb = za0; zb < za1; zb += W) {
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+      const int z = zb + r;  // A's row; B's row is z - 4
+      if (z >= za1) break;
+      if (z + PF < za1) {
+        load_centre(z + kRadius + PF, uc[(r + 8 + PF) % W], lc[(r + 8 + PF) % W]);
+        const int qn = (r + PF) % R;
+        load_pt(z + PF, uh[qn], lh[qn], p0[qn], pl[qn], pw[qn]);
+      }
+      const int sA = (r + 4) % W;  // ring slot of row z
+      const int sB = r % W;        // ring slot of row z - 4
+      const int tA = (r + 4) % W5, tB = r % W5;
+      // ---- step A at row z (all 64 columns)
+      {
+        const int qa = r % R;
+        const float cu = uc[sA], cl = lc[sA];
+        lds_put(ldsU, lane, cu, uh[qa]);
+        lds_put(ldsL, lane, cl, lh[qa]);
+        wave_lds_fence();
+        const bool inz = z >= 0 && z < d.Z;
+        const Row row = make_row(d, inz ? z : 0);
+        float lapL = laplace<W>(lc, r + 4, ldsL, lane);
+        float lapU = (inz && row.model) ? laplace<W>(uc, r + 4, ldsU, lane) : 0.0f;
+        if (z == rzA) {
+          const int tr = a.rmaps[a.rrows[rpA].map + lane];
+          if (tr >= 0) lapL += psiA[tr];
+          ++rpA;
+          rzA = rpA < rend ? a.rrows[rpA].z : INT_MAX;
+        }
+        if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lapU += fA;
+        const float w = pw[qa];
+        float lo = 0.0f, uo = 0.0f, tg = 0.0f, te = 0.0f;
+        if (inz && col.xin) {
+          const int dd = max(row.dz, col.dxs);
+          lo = dd == 0 ? fmaf(w, lapL, 2.0f * cl - pl[qa]) : sponge_update(a.sp_a, dd, cl, pl[qa], w, lapL);
+          if (dd == 0) {
+            const float D = w * lapU;
+            uo = fmaf(w, lapU, 2.0f * cu - p0[qa]);
+            tg = lo * D;
+            te = D * D;
+          } else {
+            const int ri = strip_index(row, col);
+            if (ri >= 0) uo = stripA ? stripA[ri] : 0.0f;
+          }
+        }
+        lds_put(ringU[sA], lane, uo, 0.0f);
+        lds_put(ringL[sA], lane, lo, 0.0f);
+        wr[tA] = w;
+        cg[tA] = tg;
+        ce[tA] = te;
+        go[tA] = 0.0f;
+        eo[tA] = 0.0f;
+        if (z >= z0 && z < z1 && own_col) {
+          const int64_t idx = (int64_t)z * d.P + col.xs;
+          uO0[idx] = uo;
+          lO0[idx] = lo;
+          if (row.model && col.mcol) {
+            const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
+            go[tA] = G[mi];
+            eo[tA] = first ? 0.0f : E[mi];
+          }
+        }
+      }
+      wave_lds_fence();
+      // ---- step B at row z - 4 (owned lanes)
+      const int zbB = z - kRadius;
+      if (zbB >= z0 && zbB < z1) {
+        const Row row = make_row(d, zbB);
+        const float cu = ringU[sB][kRadius + lane], cl = ringL[sB][kRadius + lane];
+        // 8th-order Laplacian from the LDS rings: rows z-8 .. z, columns +-4
+        float lapU = 0.0f, lapL = 0.0f;
+#pragma unroll
+        for (int k = 4; k >= 1; --k) {
+          const int up = (r - k + W) % W, dn = (r + k) % W;
+          const float szL = ringL[up][kRadius + lane] + ringL[dn][kRadius + lane];
+          const float sxL = ringL[sB][kRadius + lane - k] + ringL[sB][kRadius + lane + k];
+          lapL = fmaf(ck(k), fmaf(-4.0f, cl, szL + sxL), lapL);
+          if (row.model) {
+            const float szU = ringU[up][kRadius + lane] + ringU[dn][kRadius + lane];
+            const float sxU = ringU[sB][kRadius + lane - k] + ringU[sB][kRadius + lane + k];
+            lapU = fmaf(ck(k), fmaf(-4.0f, cu, szU + sxU), lapU);
+          }
+        }
+        if (zbB == rzB) {
+          const int tr = a.rmaps[a.rrows[rpB].map + lane];
+          if (tr >= 0 && hasB) lapL += psiB[tr];
+          ++rpB;
+          rzB = rpB < rend ? a.rrows[rpB].z : INT_MAX;
+        }
+        if (src_tile && zbB == sd.src_z && col.xs == sd.src_xs) lapU += fB;
+        if (own_col) {
+          const int64_t idx = (int64_t)zbB * d.P + col.xs;
+          const int dd = max(row.dz, col.dxs);
+          const float w = wr[tB];
+          const float pu = uc[sB], pl1 = lc[sB];  // u[m-1], lam[m+1] at row z - 4
+          if (dd == 0) {
+            const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
+            if (hasB) {
+              const float lo = fmaf(w, lapL, 2.0f * cl - pl1);
+              const float D = w * lapU;
+              lO1[idx] = lo;
+              uO1[idx] = fmaf(w, lapU, 2.0f * cu - pu);
+              G[mi] = fmaf(lo, D, go[tB] + cg[tB]);
+              E[mi] = fmaf(D, D, eo[tB] + ce[tB]);
+            } else {
+              G[mi] = go[tB] + cg[tB];
+              E[mi] = eo[tB] + ce[tB];
+            }
+          } else if (hasB) {
+            lO1[idx] = sponge_update(a.sp_a, dd, cl, pl1, w, lapL);
+            const int ri = strip_index(row, col);
+            if (ri >= 0) uO1[idx] = stripB ? stripB[ri] : 0.0f;
+          }
+        }
+      }
+      wave_lds_fence();
     }
   }
 }
@@ -1046,6 +1307,11 @@ hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_
     case 14: reverse_fs<3, false, true>(a, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse2(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reverse2, dim3(step_blocks(a.d, a.S)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -124,7 +124,7 @@ enum Phase { kPhaseFwd = 0, kPhaseRev = 1 };
 
 struct Layout {
   size_t hdr, shots, slots, rdir, rrows, rmaps, trace_shot;
-  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, bu, bw, rslots, total;
+  size_t w, traces, jpart, u, lam, g, E, snap, strip, xlam, xD, xI, bu, bw, rslots, rdir2, rrows2, rmaps2, total;
 };
 
 // device header at the start of every workspace
@@ -148,6 +148,9 @@ struct Plan {
   int ext_h = -1, ext_T = 0;   // extended imaging: offset bound (-1: off), ring of reverse steps
   int ext_groups = 1;          // partial images (slot groups) of the extended image
   int born = 0;                // Born perturbation wavefield buffers present
+  int rev_steps = 1;           // time steps per launch of the plain reverse sweep (1 or 2)
+  int ulevels = kULevels, llevels = kLamLevels;
+  int XT2 = 0;                 // tiles of the two-step reverse sweep along x
   double sp_a = 0.0;
   double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -161,6 +164,9 @@ struct Plan {
   std::vector<RmapDir> rdir;
   std::vector<RmapRow> rrows;
   std::vector<int32_t> rmaps;
+  std::vector<RmapDir> rdir2;  // receiver maps of the two-step tiling
+  std::vector<RmapRow> rrows2;
+  std::vector<int32_t> rmaps2;
   std::vector<int32_t> trace_shot;
   int64_t snap_stride = 0, strip_stride = 0;
   Layout L{};
@@ -175,9 +181,10 @@ struct Plan {
 };
 
 // Launch configuration: the forward sweep's shots in flight / rows per tile
-// and the reverse sweep's (Sr divides S; 0 = same as the forward's).
+// and the reverse sweep's (Sr divides S; 0 = same as the forward's), and the
+// reverse sweep's time steps per launch (1 or 2).
 struct ExecChoice {
-  int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr;
+  int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr, rsteps;
 };
 
 std::mutex g_mutex;
@@ -264,6 +271,14 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->dr = p->d;
   build_dims(*p, g, ex.TZ);
   const Dims& d = p->d;
+  // two time steps per reverse launch (the plain adjoint sweep only; not with
+  // a free surface)
+  const bool rev2 = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
+                     what == FWI_WS_GNHVP) && !plain && !g->free_surface && ex.rsteps == 2;
+  p->rev_steps = rev2 ? 2 : 1;
+  p->ulevels = rev2 ? kULevels2 : kULevels;
+  p->llevels = rev2 ? kLamLevels2 : kLamLevels;
+  p->XT2 = (d.X + kTile2 - 1) / kTile2;
   const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
   p->sp_a = 0.5 * g->dt * eta_max / ((double)d.N * d.N);
 
@@ -277,6 +292,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
     std::memset(&sd, 0, sizeof(sd));
     sd.nt = shot_nt(g, geo, s);
     sd.K = std::max(1, (int)std::ceil(std::sqrt((double)sd.nt)));
+    if (rev2) sd.K += sd.K & 1;  // two-step reverse: restarts fall on the first step of a launch
     sd.nsnap = (sd.nt - 2) / sd.K;
     max_nsnap = std::max(max_nsnap, sd.nsnap);
     sd.src_z = geo->src_iz[s] + d.N;
@@ -285,6 +301,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
     sd.nrec = geo->rec_ptr[s + 1] - geo->rec_ptr[s];
     p->max_nrec = std::max(p->max_nrec, sd.nrec);
     sd.rdir = s * d.XT;
+    sd.rdir2 = s * p->XT2;
     int zmin = g->nz, xmin = g->nx, xmax = -1;
     for (int r = sd.rec_begin; r < sd.rec_begin + sd.nrec; ++r) {
       zmin = std::min(zmin, geo->rec_iz[r]);
@@ -315,6 +332,32 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   }
   if (p->rrows.empty()) p->rrows.push_back(RmapRow{0, 0});
   if (p->rmaps.empty()) p->rmaps.assign(kWave, -1);
+  // the same for the two-step tiling: tile t computes storage columns
+  // [off - 4 + 56 t, +64), so a receiver can sit in two tiles
+  p->rdir2.assign((size_t)std::max(ns, 1) * std::max(p->XT2, 1), RmapDir{0, 0});
+  if (rev2) {
+    for (int s = 0; s < ns; ++s) {
+      std::map<std::pair<int, int>, std::vector<int>> rows;  // (tile, z) -> traces
+      for (int r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
+        const int rel = geo->rec_ix[r] + d.mx0 - (d.off - kRadius);  // >= 4
+        for (int t = std::max(0, (rel - kWave) / kTile2); t <= rel / kTile2 && t < p->XT2; ++t)
+          if (rel - kTile2 * t >= 0 && rel - kTile2 * t < kWave) rows[{t, geo->rec_iz[r] + d.N}].push_back(r);
+      }
+      for (auto& kv : rows) {
+        const int t = kv.first.first, z = kv.first.second;
+        RmapDir& dir = p->rdir2[(size_t)s * p->XT2 + t];
+        if (dir.count == 0) dir.begin = (int)p->rrows2.size();
+        dir.count++;
+        const int map = (int)p->rmaps2.size();
+        p->rrows2.push_back(RmapRow{z, map});
+        p->rmaps2.resize(map + kWave, -1);
+        for (int r : kv.second)
+          p->rmaps2[map + (geo->rec_ix[r] + d.mx0 - (d.off - kRadius) - kTile2 * t)] = r;
+      }
+    }
+  }
+  if (p->rrows2.empty()) p->rrows2.push_back(RmapRow{0, 0});
+  if (p->rmaps2.empty()) p->rmaps2.assign(kWave, -1);
 
   // batches: longest records first so that a batch's shots end together
   std::vector<int> order(ns);
@@ -372,12 +415,15 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.rdir = take(sizeof(RmapDir) * p->rdir.size());
   L.rrows = take(sizeof(RmapRow) * p->rrows.size());
   L.rmaps = take(sizeof(int32_t) * p->rmaps.size());
+  L.rdir2 = take(sizeof(RmapDir) * p->rdir2.size());
+  L.rrows2 = take(sizeof(RmapRow) * p->rrows2.size());
+  L.rmaps2 = take(sizeof(int32_t) * p->rmaps2.size());
   L.trace_shot = take(sizeof(int32_t) * p->trace_shot.size());
   L.w = take(sizeof(float) * d.field);
   L.traces = take(sizeof(float) * (size_t)g->nt_max * std::max(p->ntrace, 1));
   L.jpart = take(sizeof(double) * std::max(p->ntrace, 1));
-  L.u = take(sizeof(float) * kULevels * d.field * p->ncs);
-  L.lam = grad ? take(sizeof(float) * 2 * d.field * p->Sr) : o;
+  L.u = take(sizeof(float) * p->ulevels * d.field * p->ncs);
+  L.lam = grad ? take(sizeof(float) * p->llevels * d.field * p->Sr) : o;
   L.g = grad ? take(sizeof(float) * d.model * p->Sr) : o;
   // E per reverse slot (gradient) or per forward slot (forward-only Hessian)
   L.E = (grad || hess) ? take(sizeof(float) * d.model * (hess ? p->S : p->Sr)) : o;
@@ -399,22 +445,27 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
 template <class T>
 T* at(void* ws, size_t off) { return (T*)((char*)ws + off); }
 
-// batch: forward batch (phase kPhaseFwd) or reverse batch (kPhaseRev)
-StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* wavelet, int64_t wstride) {
+// batch: forward batch (phase kPhaseFwd) or reverse batch (kPhaseRev); two:
+// the two-step reverse sweep (its own x tiling and receiver maps)
+StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* wavelet, int64_t wstride,
+                   bool two = false) {
   StepArgs a{};
   const bool rev = phase == kPhaseRev;
   a.d = rev ? p.dr : p.d;
+  if (two) a.d.XT = p.XT2;
   a.S = rev ? p.Sr : p.S;
   a.xcd_map = rev ? p.xcd_map_r : p.xcd_map;
   a.slots = rev ? at<SlotInfo>(ws, p.L.rslots) + (size_t)batch * p.Sr
                 : at<SlotInfo>(ws, p.L.slots) + (size_t)batch * p.S;
   a.shots = at<ShotDesc>(ws, p.L.shots);
-  a.rdir = at<RmapDir>(ws, p.L.rdir);
-  a.rrows = at<RmapRow>(ws, p.L.rrows);
-  a.rmaps = at<int32_t>(ws, p.L.rmaps);
+  a.rdir = at<RmapDir>(ws, two ? p.L.rdir2 : p.L.rdir);
+  a.rrows = at<RmapRow>(ws, two ? p.L.rrows2 : p.L.rrows);
+  a.rmaps = at<int32_t>(ws, two ? p.L.rmaps2 : p.L.rmaps);
   a.w = at<float>(ws, p.L.w);
   a.u = at<float>(ws, p.L.u);
   a.lam = at<float>(ws, p.L.lam);
+  a.ustride = (int64_t)p.ulevels * p.d.field;
+  a.lstride = (int64_t)p.llevels * p.d.field;
   a.g = at<float>(ws, p.L.g);
   a.E = at<float>(ws, p.L.E);
   a.traces = at<float>(ws, p.L.traces);
@@ -471,13 +522,17 @@ hipError_t get_capture_stream(hipStream_t* out) {
 int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, const float* wavelet,
               int64_t wstride, hipStream_t stream) {
   if (nsteps <= 0) return FWI_OK;
-  StepArgs a = step_args(p, ws, batch, phase, wavelet, wstride);
+  // the plain reverse sweep of a two-step plan: launches of two steps each
+  const bool two = phase == kPhaseRev && flags == 0 && p.rev_steps == 2;
+  if (two) nsteps = (nsteps + 1) / 2;
+  StepArgs a = step_args(p, ws, batch, phase, wavelet, wstride, two);
   // reverse sweeps with kRevExt keep lam and D of the last ext_T steps and
   // fold them into the extended image after every ext_T steps
   const bool ext = phase == kPhaseRev && (flags & kRevExt);
   if (ext && p.ext_h < 0) return fail(FWI_ERR_STATE, "extended image without its buffers");
   ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
+    if (two) return launch_reverse2(args, s);
     return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
                               : launch_reverse(args, p.pf_rev, flags, s);
   };
@@ -499,7 +554,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
                                       (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
                                       (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
-                                      (uint64_t)wstride, (uint64_t)ext};
+                                      (uint64_t)wstride, (uint64_t)ext, (uint64_t)two};
   hipGraphExec_t exec = nullptr;
   auto it = p.graphs.find(gkey);
   if (it != p.graphs.end()) {
@@ -567,6 +622,12 @@ int upload_tables(const Plan& p, void* ws, hipStream_t s) {
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rmaps), p.rmaps.data(), sizeof(int32_t) * p.rmaps.size(),
                          hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rdir2), p.rdir2.data(), sizeof(RmapDir) * p.rdir2.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rrows2), p.rrows2.data(), sizeof(RmapRow) * p.rrows2.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.rmaps2), p.rmaps2.data(), sizeof(int32_t) * p.rmaps2.size(),
+                         hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(at<char>(ws, p.L.trace_shot), p.trace_shot.data(),
                          sizeof(int32_t) * p.trace_shot.size(), hipMemcpyHostToDevice, s));
   return FWI_OK;
@@ -588,7 +649,7 @@ int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s, const flo
 int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int64_t wstride,
                   hipStream_t s) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1, s));
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), p.ulevels * p.d.field, p.ulevels * p.d.field, slots, p.S, 1, s));
   if (flags & kFwdBorn)
     HIP_TRY(launch_fill_slots(at<float>(ws, p.L.bu), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1,
                               s));
@@ -616,7 +677,8 @@ int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipSt
 int reverse_batch(Plan& p, void* ws, int rb, const float* wavelet, int64_t wstride, hipStream_t s,
                   int flags = 0) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.rslots) + (size_t)rb * p.Sr;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), 2 * p.d.field, 2 * p.d.field, slots, p.Sr, 0, s));
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), p.llevels * p.d.field, p.llevels * p.d.field, slots, p.Sr, 0,
+                            s));
   return run_steps(p, ws, rb, kPhaseRev, flags, p.rbatch_nt[rb] - 1, wavelet, wstride, s);
 }
 
@@ -701,6 +763,10 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   else RFs = {1, 3};
   std::vector<int> SRs = Ss;
   if (ex && ex->shots_in_flight_reverse > 0) SRs = {ex->shots_in_flight_reverse};
+  std::vector<int> RSs;  // reverse time steps per launch
+  if (ex && ex->reverse_steps > 0) RSs = {ex->reverse_steps};
+  else if (g->free_surface) RSs = {1};
+  else RSs = {1, 2};
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
                      what == FWI_WS_GNHVP);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
@@ -711,7 +777,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
                     time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s));
   };
   struct Cand {
-    int S, TZ, pf;
+    int S, TZ, pf, rs;
     double per_shot;  // ms per shot and step
   };
   std::vector<Cand> F, Rv;
@@ -725,7 +791,8 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       const bool tr = grad && std::find(TZr.begin(), TZr.end(), TZ) != TZr.end() &&
                       std::find(SRs.begin(), SRs.end(), S) != SRs.end();
       if (!tf && !tr) continue;
-      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ};
+      const int rs_max = *std::max_element(RSs.begin(), RSs.end());
+      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max};
       auto p = build_plan(g, geo, c, 0, what, 0);
       if (p->L.total > ws_bytes) continue;
       if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
@@ -741,17 +808,21 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
           const double ms = timed(*p, fwd_flags, kPhaseFwd);
           if (ms < fb * 0.98) { fb = ms; fpf = pf; }
         }
-        F.push_back(Cand{S, TZ, fpf, fb / shots});
+        F.push_back(Cand{S, TZ, fpf, 1, fb / shots});
       }
       if (tr) {
         double rb = 1e30;
-        int rpf = RFs[0];
-        for (int pf : RFs) {
-          p->pf_rev = pf;
-          const double ms = timed(*p, 0, kPhaseRev);
-          if (ms < rb * 0.98) { rb = ms; rpf = pf; }
+        int rpf = RFs[0], rrs = RSs[0];
+        for (int rs : RSs) {
+          // the two-step sweep has one prefetch depth of its own
+          for (int pf : (rs == 2 ? std::vector<int>{RFs[0]} : RFs)) {
+            p->rev_steps = rs;
+            p->pf_rev = pf;
+            const double ms = timed(*p, 0, kPhaseRev);
+            if (ms < rb * 0.98) { rb = ms; rpf = pf; rrs = rs; }
+          }
         }
-        Rv.push_back(Cand{S, TZ, rpf, rb / shots});
+        Rv.push_back(Cand{S, TZ, rpf, rrs, rb / shots});
       }
     }
   }
@@ -764,7 +835,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     if (!grad) {
       if (f.per_shot < best_t * 0.98) {
         best_t = f.per_shot;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ};
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ, 1};
       }
       continue;
     }
@@ -773,7 +844,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       const double t = f.per_shot + r.per_shot;
       if (t < best_t * 0.98) {
         best_t = t;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ};
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ, r.rs};
       }
     }
   }
@@ -797,6 +868,7 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.pf_rev = (ex && ex->prefetch_reverse > 0) ? ex->prefetch_reverse : 1;
   c.Sr = (ex && ex->shots_in_flight_reverse > 0) ? ex->shots_in_flight_reverse : 0;
   c.TZr = (ex && ex->tile_rows_reverse > 0) ? ex->tile_rows_reverse : 0;
+  c.rsteps = (ex && ex->reverse_steps > 0) ? ex->reverse_steps : 1;
   return c;
 }
 
@@ -812,7 +884,8 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
                              (uint64_t)(ex ? ex->tile_rows : 0), (uint64_t)(ex ? ex->prefetch : 0),
                              (uint64_t)(ex ? ex->prefetch_reverse : 0),
                              (uint64_t)(ex ? ex->shots_in_flight_reverse : 0),
-                             (uint64_t)(ex ? ex->tile_rows_reverse : 0)};
+                             (uint64_t)(ex ? ex->tile_rows_reverse : 0),
+                             (uint64_t)(ex ? ex->reverse_steps : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -834,7 +907,7 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
 
 // Tuned choices persist across processes in a plain text file named by the
 // environment variable FWI_TUNE_CACHE: one line per key,
-//   "<key words in hex> : S TZ graph_steps prefetch prefetch_reverse S_rev TZ_rev".
+//   "<key words in hex> : S TZ graph_steps prefetch prefetch_reverse S_rev TZ_rev reverse_steps".
 std::string key_text(const std::vector<uint64_t>& k) {
   std::string out;
   char buf[24];
@@ -858,8 +931,9 @@ bool cache_lookup(const std::vector<uint64_t>& k, ExecChoice& c) {
     if (!colon) continue;
     if (std::string(line, colon - line) != want) continue;
     ExecChoice t{};
-    if (sscanf(colon + 1, "%d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
-               &t.TZr) == 7 &&
+    if (sscanf(colon + 1, "%d %d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
+               &t.TZr, &t.rsteps) == 8 &&
+        (t.rsteps == 1 || t.rsteps == 2) &&
         t.Sr > 0 && t.S % t.Sr == 0 && t.TZr >= 8 && t.TZr <= 4096 &&
         t.S > 0 && t.TZ >= 8 && t.TZ <= 4096 && (t.graph_steps == -1 || (t.graph_steps > 0 && t.graph_steps <= 1024)) &&
         (t.pf_fwd == 1 || t.pf_fwd == 3 || t.pf_fwd == 7) &&
@@ -877,8 +951,8 @@ void cache_store(const std::vector<uint64_t>& k, const ExecChoice& c) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s: %d %d %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev,
-          c.Sr, c.TZr);
+  fprintf(f, "%s: %d %d %d %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev,
+          c.Sr, c.TZr, c.rsteps);
   fclose(f);
 }
 
@@ -896,6 +970,7 @@ int check_exec(const fwi_exec* ex) {
     return fail(FWI_ERR_ARG, "prefetch must be 0, 1, 3 or 7");
   if (ex && ex->prefetch_reverse != 0 && ex->prefetch_reverse != 1 && ex->prefetch_reverse != 3)
     return fail(FWI_ERR_ARG, "prefetch_reverse must be 0, 1 or 3");
+  if (ex && (ex->reverse_steps < 0 || ex->reverse_steps > 2)) return fail(FWI_ERR_ARG, "reverse_steps must be 0, 1 or 2");
   return FWI_OK;
 }
 
@@ -913,6 +988,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     if (!(ex->shots_in_flight > 0)) c.S = std::min(std::max(geo->nshot, 1), 64);
     if (!(ex->tile_rows > 0)) c.TZ = 32;
     c.Sr = 0;  // reverse buffers sized for the forward's maximum
+    if (!(ex->reverse_steps > 0)) c.rsteps = 2;  // and for the two-step sweep's levels
   }
   if (tune) {
     const auto tk = tune_key(g, geo, ex, what);
@@ -943,6 +1019,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.pf_rev);
   h.pod(c.Sr);
   h.pod(c.TZr);
+  h.pod(c.rsteps);
   h.pod(ext_h);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
@@ -1031,6 +1108,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
     if (S % Sr) Sr = S;
     chosen->shots_in_flight_reverse = Sr;
     chosen->tile_rows_reverse = c.TZr > 0 ? c.TZr : c.TZ;
+    chosen->reverse_steps = (plain || grid->free_surface) ? 1 : c.rsteps;
   }
   return FWI_OK;
 }

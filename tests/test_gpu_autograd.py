@@ -24,7 +24,8 @@ def anomaly():
 
 
 @pytest.mark.parametrize("exec_", [None, B.make_exec(graph_steps=-1), B.make_exec(mode=B.EXEC_PLAIN),
-                                   B.make_exec(shots_in_flight=2, shots_in_flight_reverse=1, tile_rows_reverse=12)])
+                                   B.make_exec(shots_in_flight=2, shots_in_flight_reverse=1, tile_rows_reverse=12),
+                                   B.make_exec(reverse_steps=2, graph_steps=7)])
 def test_autograd_matches_oracle(anomaly, exec_):
     w, d_obs, (J, g, H1, E, syn) = anomaly
     pr = FWIProblem(w.grid, w.geom, w.wavelet, d_obs.astype(np.float32), "int", exec_, hmax=4)
