@@ -5,7 +5,11 @@
 // row-major with pitch P floats; padded column x lives at storage column
 // x + off, where `off` is chosen so that the model's first column (x = N)
 // starts a 64-float (256-byte) line.  Storage columns outside [off, off + X)
-// are held at zero and implement the zero boundary beyond the sponge.
+// are held at zero and implement the zero boundary beyond the sponge; there
+// are at least 4 of them on either side (off >= 4, P >= off + X + 4), and
+// every wavefield level is followed by kGuardRows zero rows (the first level
+// is also preceded by them).  A stencil load of a row or column just outside
+// the grid therefore reads zeros from memory, without a test or a select.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -27,6 +31,10 @@ constexpr int kLamLevels2 = 4;
 // output columns of a two-step reverse tile: the wavefront computes the first
 // step on 64 columns and the second on the 56 inside them
 constexpr int kTile2 = kWave - 2 * kRadius;
+// zero rows after each wavefield level (and before the first one): covers the
+// sweep's loads of rows -4 - 1 .. Z - 1 + 4 + 7 + 1 (stencil reach, the
+// longest prefetch and a halo column wrapping into the next row)
+constexpr int kGuardRows = 16;
 
 struct Dims {
   int32_t nz, nx, N;     // model rows / columns, sponge width
@@ -37,7 +45,8 @@ struct Dims {
   int32_t ring;          // floats of one boundary-strip ring: 8 (nx + nz)
   int32_t fs;            // free surface: rows above the model mirror it (odd image)
   int32_t ztop;          // first computed padded row: N with a free surface, else 0
-  int64_t field;         // floats per field level: Z * P
+  int64_t field;         // floats per field level: (Z + kGuardRows) * P
+  int64_t guard;         // floats of the guard rows: kGuardRows * P
   int64_t model;         // floats per model-grid array: nz * nx
 };
 

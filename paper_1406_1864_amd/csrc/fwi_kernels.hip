@@ -88,6 +88,8 @@ struct Col {
   int side;    // strip index base of a left/right ring column, -1 otherwise
   int hcol;    // halo column held by lanes 0..7
   bool hok;    // this lane loads a halo value
+  int hsafe;   // column a lane's halo load reads: hcol (lanes 0..7), else its own column
+  int mxc;     // model column clamped into [0, nx): in-bounds model-grid loads
 };
 
 __device__ __forceinline__ Col make_col(const Dims& d, int xs0, int lane) {
@@ -102,6 +104,8 @@ __device__ __forceinline__ Col make_col(const Dims& d, int xs0, int lane) {
            : (c.mx >= d.nx && c.mx < d.nx + kRadius) ? 8 * d.nx + 4 * d.nz + (c.mx - d.nx) : -1;
   c.hcol = lane < 4 ? xs0 - 4 + lane : xs0 + 60 + lane;
   c.hok = lane < 8 && c.hcol >= 0 && c.hcol < d.P;
+  c.hsafe = lane < 8 ? c.hcol : c.xs;
+  c.mxc = min(max(c.mx, 0), d.nx - 1);
   return c;
 }
 
@@ -116,6 +120,9 @@ __device__ __forceinline__ int image_row(const Dims& d, int r, float& sg) {
   }
   return r;
 }
+
+// row index clamped into the padded grid, for loads issued whatever the row
+__device__ __forceinline__ int clamp_row(const Dims& d, int r) { return min(max(r, 0), d.Z - 1); }
 
 // Uniform classification of one padded row.
 struct Row {
@@ -244,33 +251,26 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
 
   float wc[W], wh[W], pd[R], pw[R];
   float bc[BORN ? W : 1], bh[BORN ? W : 1], pbd[BORN ? R : 1], pbw[BORN ? R : 1];
+  // rows and halo columns just outside the grid read the zero guard rows and
+  // columns of the layout; the point-wise operands of rows past the grid are
+  // loaded from its last row and never used
   auto load_row = [&](int r, float& c, float& h) {
-    if (r >= 0 && r < d.Z) {
-      const float* row = ucur + (int64_t)r * d.P;
-      c = row[col.xs];
-      h = col.hok ? row[col.hcol] : 0.0f;
-    } else {
-      c = 0.0f;
-      h = 0.0f;
-    }
+    const float* row = ucur + (int64_t)r * d.P;
+    c = row[col.xs];
+    h = row[col.hsafe];
   };
   auto load_brow = [&](int r, float& c, float& h) {
-    if (r >= 0 && r < d.Z) {
-      const float* row = bcur + (int64_t)r * d.P;
-      c = row[col.xs];
-      h = col.hok ? row[col.hcol] : 0.0f;
-    } else {
-      c = 0.0f;
-      h = 0.0f;
-    }
+    const float* row = bcur + (int64_t)r * d.P;
+    c = row[col.xs];
+    h = row[col.hsafe];
   };
   auto load_pt = [&](int r, float& p, float& w) {
-    const int64_t idx = (int64_t)r * d.P + col.xs;
+    const int64_t idx = (int64_t)clamp_row(d, r) * d.P + col.xs;
     p = dinc[idx];
     w = a.w[idx];
   };
   auto load_bpt = [&](int r, float& p, float& f) {
-    const int64_t idx = (int64_t)r * d.P + col.xs;
+    const int64_t idx = (int64_t)clamp_row(d, r) * d.P + col.xs;
     p = binc[idx];
     f = a.bw[idx];
   };
@@ -299,24 +299,24 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < PF; ++j)
-    if (z0 + j < z1) {
-      load_pt(z0 + j, pd[j], pw[j]);
-      if (BORN) load_bpt(z0 + j, pbd[j % (BORN ? R : 1)], pbw[j % (BORN ? R : 1)]);
-    }
+  for (int j = 0; j < PF; ++j) {
+    load_pt(z0 + j, pd[j], pw[j]);
+    if (BORN) load_bpt(z0 + j, pbd[j % (BORN ? R : 1)], pbw[j % (BORN ? R : 1)]);
+  }
 
   for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
       const int z = zb + r;
       if (z >= z1) break;
-      if (z + PF < z1) {
-        load_row(z + 4 + PF, wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
-        load_pt(z + PF, pd[(r + PF) % R], pw[(r + PF) % R]);
-        if (BORN) {
-          load_brow(z + 4 + PF, bc[(r + 8 + PF) % (BORN ? W : 1)], bh[(r + 8 + PF) % (BORN ? W : 1)]);
-          load_bpt(z + PF, pbd[(r + PF) % (BORN ? R : 1)], pbw[(r + PF) % (BORN ? R : 1)]);
-        }
+      // the next rows' loads are issued on every row, also past the tile
+      // (clamped into the grid): with the same loads on every path the
+      // compiler waits only for the rows consumed now
+      load_row(z + 4 + PF, wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
+      load_pt(z + PF, pd[(r + PF) % R], pw[(r + PF) % R]);
+      if (BORN) {
+        load_brow(z + 4 + PF, bc[(r + 8 + PF) % (BORN ? W : 1)], bh[(r + 8 + PF) % (BORN ? W : 1)]);
+        load_bpt(z + PF, pbd[(r + PF) % (BORN ? R : 1)], pbw[(r + PF) % (BORN ? R : 1)]);
       }
       const float c = wc[(r + 4) % W];
       lds_put(lds, lane, c, wh[(r + 4) % W]);
@@ -459,40 +459,33 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   }
   const float* psi = a.traces + (int64_t)m * a.ntrace;
 
-  const int uz_lo = d.N - kRadius, uz_hi = d.N + d.nz + kRadius;  // rows where u is defined
   float uc[W], uh[W], lc[W], lh[W];
   float p0[R], pl[R], pw[R], pg[R], pe[R];
+  // Every row issues the same loads and no loaded value goes through a
+  // select, so the compiler waits only for the rows consumed now, never for
+  // the prefetch: rows and halo columns just outside the grid read the zero
+  // guard rows and columns of the layout; u outside the model rows +-4 is
+  // loaded as it is (the forward's sponge values) and never used, since only
+  // model rows take the Laplacian of u; model-grid indices are clamped.
   auto load_rows = [&](int r, float& cu, float& hu, float& cl, float& hl) {
-    if (r >= 0 && r < d.Z) {
-      const int64_t ro = (int64_t)r * d.P;
-      cl = l_p1[ro + col.xs];
-      hl = col.hok ? l_p1[ro + col.hcol] : 0.0f;
-      if (r >= uz_lo && r < uz_hi) {
-        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
-        const int64_t mo = (int64_t)(r - d.N) * d.nx;
-        cu = (mrow && col.mcol) ? snap1[mo + col.mx] : u_m1[ro + col.xs];
-        hu = col.hok ? ((mrow && hmcol) ? snap1[mo + hmx] : u_m1[ro + col.hcol]) : 0.0f;
-      } else {
-        cu = 0.0f;
-        hu = 0.0f;
-      }
-    } else {
-      cu = hu = cl = hl = 0.0f;
-    }
+    const int64_t ro = (int64_t)r * d.P;
+    const bool mrow = reset && r >= d.N && r < d.N + d.nz;
+    const int64_t mo = (int64_t)min(max(r - d.N, 0), d.nz - 1) * d.nx;
+    cl = l_p1[ro + col.xs];
+    hl = l_p1[ro + col.hsafe];
+    cu = *((mrow && col.mcol) ? snap1 + mo + col.mx : u_m1 + ro + col.xs);
+    hu = *((mrow && hmcol) ? snap1 + mo + hmx : u_m1 + ro + col.hsafe);
   };
+  // operands of the update of row r (model-cell values only used there)
   auto load_pt = [&](int r, float& u0, float& l2, float& w, float& g, float& e) {
-    const int64_t idx = (int64_t)r * d.P + col.xs;
+    const int rc = clamp_row(d, r);
+    const int64_t idx = (int64_t)rc * d.P + col.xs;
+    const int64_t mi = (int64_t)min(max(rc - d.N, 0), d.nz - 1) * d.nx + col.mxc;
     l2 = l_p2[idx];
     w = a.w[idx];
-    const int mz = r - d.N;
-    if (mz >= 0 && mz < d.nz && col.mcol) {
-      const int64_t mi = (int64_t)mz * d.nx + col.mx;
-      u0 = u0src ? u0src[mi] : u_m[idx];
-      g = G[mi];
-      e = first ? 0.0f : E[mi];
-    } else {
-      u0 = g = e = 0.0f;
-    }
+    u0 = *(u0src ? u0src + mi : u_m + idx);
+    g = G[mi];
+    e = E[mi];  // replaced by 0 on the first step where it is used
   };
   // only the first window of the top tile reaches above the model (free
   // surface: odd image); elsewhere the loads go out back to back
@@ -511,15 +504,14 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
     for (int j = 0; j < 8 + PF; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
   }
 #pragma unroll
-  for (int j = 0; j < PF; ++j)
-    if (z0 + j < z1) load_pt(z0 + j, p0[j], pl[j], pw[j], pg[j], pe[j]);
+  for (int j = 0; j < PF; ++j) load_pt(z0 + j, p0[j], pl[j], pw[j], pg[j], pe[j]);
 
   for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
       const int z = zb + r;
       if (z >= z1) break;
-      if (z + PF < z1) {
+      {
         const int s = (r + 8 + PF) % W, q = (r + PF) % R;
         load_rows(z + 4 + PF, uc[s], uh[s], lc[s], lh[s]);
         load_pt(z + PF, p0[q], pl[q], pw[q], pg[q], pe[q]);
@@ -533,13 +525,13 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
       float lapL = laplace<W>(lc, r + 4, ldsL, lane);
       const float lapU0 = row.model ? laplace<W>(uc, r + 4, ldsU, lane) : 0.0f;
       wave_lds_fence();
-      int tr = -1;
+      // receiver row (rare): the adjoint source is read and waited for here
       if (z == rz) {
-        tr = a.rmaps[a.rrows[rp].map + lane];
+        const int tr = a.rmaps[a.rrows[rp].map + lane];
+        if (tr >= 0) lapL += psi[tr];
         ++rp;
         rz = rp < rend ? a.rrows[rp].z : INT_MAX;
       }
-      if (tr >= 0) lapL += psi[tr];
       float lapU = lapU0;
       if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lapU += fsrc;
 
@@ -556,7 +548,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
           const float D = wv_ * lapU;
           u_m[idx] = fmaf(wv_, lapU, 2.0f * cu - p0[q]);
           G[mi] = fmaf(lout, IMGU ? cu : D, pg[q]);
-          E[mi] = fmaf(D, D, pe[q]);
+          E[mi] = fmaf(D, D, first ? 0.0f : pe[q]);
           if (EXT) {
             const int64_t xo = ((int64_t)slot * a.ext_T + ext_slot) * d.model + mi;
             a.ext_lam[xo] = lout;
@@ -1004,7 +996,7 @@ __global__ void k_prep(Dims d, const float* __restrict__ v, float* __restrict__ 
   if (i >= d.field) return;
   const int z = (int)(i / d.P), xs = (int)(i % d.P), x = xs - d.off;
   float out = 0.0f;
-  if (x >= 0 && x < d.X) {
+  if (x >= 0 && x < d.X && z < d.Z) {
     const int iz = min(max(z - d.N, 0), d.nz - 1), ix = min(max(x - d.N, 0), d.nx - 1);
     const float vv = v[(int64_t)iz * d.nx + ix];
     if (!(vv > 0.0f && vv <= vmax)) atomicOr(err, 1);

@@ -234,15 +234,17 @@ void build_dims(Plan& p, const fwi_grid* g, int TZ) {
   d.Z = d.nz + 2 * d.N;
   d.X = d.nx + 2 * d.N;
   d.off = (kWave - d.N % kWave) % kWave;
+  if (d.off < kRadius) d.off += kWave;  // zero columns to the left of the grid
   d.mx0 = d.off + d.N;
-  d.P = (int)align_up(d.off + d.X, kWave);
+  d.P = (int)align_up(d.off + d.X + kRadius, kWave);
   d.XT = d.P / kWave;
   d.TZ = TZ;
   d.fs = g->free_surface ? 1 : 0;
   d.ztop = d.fs ? d.N : 0;
   d.ZT = (d.Z - d.ztop + TZ - 1) / TZ;
   d.ring = 8 * (d.nx + d.nz);
-  d.field = (int64_t)d.Z * d.P;
+  d.field = (int64_t)(d.Z + kGuardRows) * d.P;
+  d.guard = (int64_t)kGuardRows * d.P;
   d.model = (int64_t)d.nz * d.nx;
 }
 
@@ -422,8 +424,9 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   L.w = take(sizeof(float) * d.field);
   L.traces = take(sizeof(float) * (size_t)g->nt_max * std::max(p->ntrace, 1));
   L.jpart = take(sizeof(double) * std::max(p->ntrace, 1));
-  L.u = take(sizeof(float) * p->ulevels * d.field * p->ncs);
-  L.lam = grad ? take(sizeof(float) * p->llevels * d.field * p->Sr) : o;
+  // wavefields: guard rows in front of the first level
+  L.u = take(sizeof(float) * (p->ulevels * d.field * p->ncs + d.guard));
+  L.lam = grad ? take(sizeof(float) * (p->llevels * d.field * p->Sr + d.guard)) : o;
   L.g = grad ? take(sizeof(float) * d.model * p->Sr) : o;
   // E per reverse slot (gradient) or per forward slot (forward-only Hessian)
   L.E = (grad || hess) ? take(sizeof(float) * d.model * (hess ? p->S : p->Sr)) : o;
@@ -436,7 +439,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   // up to 4 slot groups fold in parallel for |h| <= 16 (one for larger offsets)
   p->ext_groups = ext ? (p->ext_h <= 16 ? std::min(p->Sr, 4) : 1) : 1;
   L.xI = ext ? take(sizeof(float) * d.model * (2 * p->ext_h + 1) * p->ext_groups) : o;
-  L.bu = p->born ? take(sizeof(float) * kULevels * d.field * p->ncs) : o;
+  L.bu = p->born ? take(sizeof(float) * (kULevels * d.field * p->ncs + d.guard)) : o;
   L.bw = p->born ? take(sizeof(float) * d.field) : o;
   L.total = o;
   return p;
@@ -462,8 +465,8 @@ StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* w
   a.rrows = at<RmapRow>(ws, two ? p.L.rrows2 : p.L.rrows);
   a.rmaps = at<int32_t>(ws, two ? p.L.rmaps2 : p.L.rmaps);
   a.w = at<float>(ws, p.L.w);
-  a.u = at<float>(ws, p.L.u);
-  a.lam = at<float>(ws, p.L.lam);
+  a.u = at<float>(ws, p.L.u) + p.d.guard;
+  a.lam = at<float>(ws, p.L.lam) + p.d.guard;
   a.ustride = (int64_t)p.ulevels * p.d.field;
   a.lstride = (int64_t)p.llevels * p.d.field;
   a.g = at<float>(ws, p.L.g);
@@ -483,7 +486,7 @@ StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* w
   a.ext_lam = p.ext_h >= 0 ? at<float>(ws, p.L.xlam) : nullptr;
   a.ext_D = p.ext_h >= 0 ? at<float>(ws, p.L.xD) : nullptr;
   a.ext_T = p.ext_T;
-  a.bu = p.born ? at<float>(ws, p.L.bu) : nullptr;
+  a.bu = p.born ? at<float>(ws, p.L.bu) + p.d.guard : nullptr;
   a.bw = p.born ? at<float>(ws, p.L.bw) : nullptr;
   return a;
 }
@@ -649,10 +652,11 @@ int begin_call(const Plan& p, void* ws, const float* v, hipStream_t s, const flo
 int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int64_t wstride,
                   hipStream_t s) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.slots) + (size_t)b * p.S;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), p.ulevels * p.d.field, p.ulevels * p.d.field, slots, p.S, 1, s));
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.u), p.ulevels * p.d.field, p.ulevels * p.d.field + p.d.guard, slots,
+                            p.S, 1, s));
   if (flags & kFwdBorn)
-    HIP_TRY(launch_fill_slots(at<float>(ws, p.L.bu), kULevels * p.d.field, kULevels * p.d.field, slots, p.S, 1,
-                              s));
+    HIP_TRY(launch_fill_slots(at<float>(ws, p.L.bu), kULevels * p.d.field, kULevels * p.d.field + p.d.guard, slots,
+                              p.S, 1, s));
   return run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
 }
 
@@ -677,8 +681,8 @@ int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipSt
 int reverse_batch(Plan& p, void* ws, int rb, const float* wavelet, int64_t wstride, hipStream_t s,
                   int flags = 0) {
   const SlotInfo* slots = at<SlotInfo>(ws, p.L.rslots) + (size_t)rb * p.Sr;
-  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), p.llevels * p.d.field, p.llevels * p.d.field, slots, p.Sr, 0,
-                            s));
+  HIP_TRY(launch_fill_slots(at<float>(ws, p.L.lam), p.llevels * p.d.field, p.llevels * p.d.field + p.d.guard, slots,
+                            p.Sr, 0, s));
   return run_steps(p, ws, rb, kPhaseRev, flags, p.rbatch_nt[rb] - 1, wavelet, wstride, s);
 }
 
