@@ -28,9 +28,13 @@ constexpr int kULevels = 3;
 constexpr int kULevels2 = 5;
 constexpr int kLamLevels = 2;
 constexpr int kLamLevels2 = 4;
-// output columns of a two-step reverse tile: the wavefront computes the first
-// step on 64 columns and the second on the 56 inside them
-constexpr int kTile2 = kWave - 2 * kRadius;
+// two-step reverse sweep: a workgroup's 4 wavefronts compute the first step
+// on 256 adjacent columns and the second on the 248 inside them; wave tile t
+// starts at storage column off - 4 + kBlk2 (t / 4) + 64 (t % 4)
+constexpr int kBlk2 = kWavesPerBlock * kWave - 2 * kRadius;
+__host__ __device__ inline int tile2_x0(int off, int t) {
+  return off - kRadius + kBlk2 * (t / kWavesPerBlock) + kWave * (t % kWavesPerBlock);
+}
 // zero rows after each wavefield level (and before the first one): covers the
 // sweep's loads of rows -4 - 1 .. Z - 1 + 4 + 7 + 1 (stencil reach, the
 // longest prefetch and a halo column wrapping into the next row)

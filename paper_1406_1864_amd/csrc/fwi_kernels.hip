@@ -26,6 +26,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "fwi_internal.h"
 
@@ -43,6 +44,18 @@ __device__ __forceinline__ float ck(int k) {
 }
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>): a loop
+// unrolled by construction, whatever the size of its body (register rings
+// indexed by the loop counter need every index to be a constant)
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // Wavefront-local LDS exchange: LDS operations of one wavefront complete in
 // program order, so only compiler reordering has to be prevented.
@@ -566,29 +579,59 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
 // -------------------------------------------------------------------------
 // Two reverse steps per launch, A = step m and B = step m-1 (temporal
 // blocking: the four field levels are read once and written once for two
-// steps, and g, E are updated once).  A wavefront computes step A on 64
-// columns and step B on the 56 inside them (lanes 4..59 own the output), so
-// B's horizontal neighbours are A's own results, exchanged through the
-// wavefront's LDS row; along z, A runs 4 rows ahead of B and over 4 more
-// rows on either side of the tile.  A's results of the last 10 rows stay in
-// registers for B's vertical stencil.  The sweep reads one pair of u and lam
-// levels and writes the other pair (alternating from launch to launch),
-// because neighbouring tiles read the inputs in their overlap.  Snapshot
-// restarts fall on A (even snapshot spacing), so B restarts from A's
-// registers.  Launch q runs A at m = nt-1-2q; B is skipped when m = 1.
+// steps, and g, E are updated once).  A workgroup's 4 wavefronts compute step
+// A on 256 adjacent columns and step B on the 248 inside them, so B's
+// horizontal neighbours are A's own results; the rows of A's inputs and of
+// A's results are exchanged through the workgroup's LDS (one barrier per
+// row), and only the outer wavefronts load halo columns.  Along z, A runs 4
+// rows ahead of B and over 4 more rows on either side of the band; A's
+// results of the last 10 rows stay in register rings for B's vertical
+// stencil, beside A's input window, which also holds B's point-wise operands
+// u[m-1], lam[m+1].  The sweep reads one pair of u and lam levels and writes
+// the other pair (alternating from launch to launch), because neighbouring
+// workgroups read the inputs in their overlap.  Snapshot restarts fall on A
+// (even snapshot spacing); the launch before a restart stores the snapshot's
+// u[a_k], u[a_k - 1] into the model cells of the levels it writes, so no
+// launch reads snapshots.  Launch q runs A at m = nt-1-2q; B is skipped when
+// m = 1.
+// A row whose update is the plain interior FMA on every lane of a wavefront
+// (a model row of columns inside the model, without receiver or source)
+// takes a branch-free path; the other rows the general one (sponge in FP64,
+// strip ring, zero boundary, receivers, source).
 // -------------------------------------------------------------------------
+// Buffer-resource addressing: a uniform base (4 SGPRs), a per-lane 32-bit
+// byte offset fixed for the whole sweep and a uniform 32-bit byte offset per
+// row, so that a load costs no per-lane address arithmetic.  The resource
+// covers the array; every offset used here stays inside it.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const float* base, int64_t floats) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)(floats * 4), 0x00020000);
+}
+__device__ __forceinline__ float bld(rsrc_t r, uint32_t voff, int32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, 0);
+}
+
+// LDS row exchange without lane tests: lanes 0..7 write their halo value to
+// its slot, the other lanes to their own slot, which the centre value then
+// overwrites (LDS operations of one wavefront complete in order)
+__device__ __forceinline__ void lds_put_nb(float* lds, int hidx, int lane, float c, float h) {
+  lds[hidx] = h;
+  lds[kRadius + lane] = c;
+}
+
 __global__ __launch_bounds__(256) void k_reverse2(StepArgs a) {
-  constexpr int PF = 1;
-  constexpr int W = 9 + PF;  // rows of the stencil rings
-  constexpr int R = PF + 1;  // rows of the point-wise rings
-  constexpr int W5 = 5;      // rows between A and B, plus one
-  constexpr int LR = kWave + 2 * kRadius;
-  static_assert(W % R == 0 && W % W5 == 0, "ring lengths must divide the unrolled period");
-  __shared__ float ldsU_all[kWavesPerBlock][LR];
-  __shared__ float ldsL_all[kWavesPerBlock][LR];
-  // A's results u[m-2], lam[m] of the last W rows: B's stencil operands
-  __shared__ float ringU_all[kWavesPerBlock][W][LR];
-  __shared__ float ringL_all[kWavesPerBlock][W][LR];
+  constexpr int PF = 1;      // rows of loads in flight ahead of A
+  constexpr int W = 10;      // register rings: the unrolled period
+  constexpr int R = PF + 1;  // point-wise rings
+  constexpr int LR = kWavesPerBlock * kWave + 2 * kRadius;
+  constexpr int CB = 2 * kRadius;  // column bias of the lane offsets (halo columns reach -4)
+  // the workgroup's rows of A's inputs (u, lam) and of A's results (for B),
+  // 256 columns plus the 4-column halos; rows alternate between two buffer
+  // sets, so that one barrier per row suffices
+  __shared__ float xrow[2][4][LR];
   const int lane = threadIdx.x & 63;
   const int wv = uniform(threadIdx.x >> 6);
   int slot, tile;
@@ -603,223 +646,281 @@ __global__ __launch_bounds__(256) void k_reverse2(StepArgs a) {
   const bool hasB = m >= 2;
 
   const Dims& d = a.d;
-  float* ldsU = ldsU_all[wv];
-  float* ldsL = ldsL_all[wv];
-  float (*ringU)[LR] = ringU_all[wv];
-  float (*ringL)[LR] = ringL_all[wv];
-  const int xt = tile % d.XT, zt = tile / d.XT;
-  // lane 0's storage column: the owned lanes 4..59 of tile xt start at padded column 56 xt
-  const int xs0 = d.off - kRadius + kTile2 * xt;
-  const Col col = make_col(d, xs0, lane);
-  const bool own_col = lane >= kRadius && lane < kWave - kRadius && col.xin;
-  const int hmx = col.hcol - d.mx0;
-  const bool hmcol = hmx >= 0 && hmx < d.nx;
+  const int xt = tile % d.XT, zt = tile / d.XT;  // xt % 4 == wv: the workgroup's columns
+  // lane 0's storage column; B owns the workgroup's columns 4 .. 251
+  const int xs0 = tile2_x0(d.off, xt);
+  Col col = make_col(d, xs0, lane);
+  const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
+  // only the outer wavefronts load halo columns (wave 0 lanes 0..3 the left,
+  // the last wave lanes 4..7 the right one); the others load their own column
+  const bool hl_lane = (wv == 0 && lane < 4) || (wv == kWavesPerBlock - 1 && lane >= 4 && lane < 8);
+  col.hsafe = hl_lane ? col.hcol : col.xs;
+  const int cidx = kRadius + kWave * wv + lane;  // this lane's slot in the workgroup rows
+  const int hidx = hl_lane ? (lane < 4 ? lane : kWavesPerBlock * kWave + lane) : cidx;
   const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);  // B's (owned) rows
   const int za0 = z0 - kRadius, za1 = z1 + kRadius;    // A's rows
+  const int mz_lo = d.N, mz_hi = d.N + d.nz;           // model rows
+  const bool tile_int = xs0 >= d.mx0 && xs0 + kWave <= d.mx0 + d.nx;  // every lane a model column
+  // the tile reaches the strip ring around the model (its columns or its rows)
+  const bool ring_cols = (xs0 < d.mx0 && xs0 + kWave > d.mx0 - kRadius) ||
+                         (xs0 < d.mx0 + d.nx + kRadius && xs0 + kWave > d.mx0 + d.nx);
+  const bool ring_rows = (za0 < mz_lo && za1 > mz_lo - kRadius) || (za0 < mz_hi + kRadius && za1 > mz_hi);
+  const bool ring = ring_cols || ring_rows;
 
   // level pairs: launches with even q read the pair the forward sweep left
   // (u[k] at level k & 1) and write levels 3, 4; odd q the other way round
   const bool even = (q & 1) == 0;
+  const int uA0 = even ? (m & 1) : 3;        // u[m]
+  const int uA1 = even ? ((m - 1) & 1) : 4;  // u[m-1]
+  const int uO0 = even ? 3 : (m & 1);        // u[m-2]
+  const int uO1 = even ? 4 : ((m - 1) & 1);  // u[m-3]
+  const int lA1 = even ? ((m + 1) & 1) : 3;  // lam[m+1]
+  const int lA2 = even ? (m & 1) : 2;        // lam[m+2]
+  const int lO0 = even ? 2 : (m & 1);        // lam[m]
+  const int lO1 = even ? 3 : ((m + 1) & 1);  // lam[m-1]
   float* ubase = a.u + (int64_t)si.cs * a.ustride;
-  const float* uA0 = ubase + (int64_t)(even ? (m & 1) : 3) * d.field;        // u[m]
-  const float* uA1 = ubase + (int64_t)(even ? ((m - 1) & 1) : 4) * d.field;  // u[m-1]
-  float* uO0 = ubase + (int64_t)(even ? 3 : (m & 1)) * d.field;              // u[m-2]
-  float* uO1 = ubase + (int64_t)(even ? 4 : ((m - 1) & 1)) * d.field;        // u[m-3]
   float* lbase = a.lam + (int64_t)slot * a.lstride;
-  const float* lA1 = lbase + (int64_t)(even ? ((m + 1) & 1) : 3) * d.field;  // lam[m+1]
-  const float* lA2 = lbase + (int64_t)(even ? (m & 1) : 2) * d.field;        // lam[m+2]
-  float* lO0 = lbase + (int64_t)(even ? 2 : (m & 1)) * d.field;              // lam[m]
-  float* lO1 = lbase + (int64_t)(even ? 3 : ((m + 1) & 1)) * d.field;        // lam[m-1]
-
-  const int rem = sd.nt - 1 - m;
-  const bool reset = rem > 0 && (rem % sd.K) == 0 && rem / sd.K <= sd.nsnap;
-  const float* ckpt = a.snap + (int64_t)si.cs * a.snap_stride;
-  const float* snap0 = reset ? ckpt + (int64_t)(rem / sd.K - 1) * 2 * d.model : nullptr;
-  const float* snap1 = reset ? snap0 + d.model : nullptr;
-  const float* strip_base = a.strip + (int64_t)si.cs * a.strip_stride;
-  const float* stripA = (m >= 3) ? strip_base + (int64_t)(m - 2) * d.ring : nullptr;
-  const float* stripB = (m >= 4) ? strip_base + (int64_t)(m - 3) * d.ring : nullptr;
-  const bool first = (m == sd.nt - 1);
   float* G = a.g + (int64_t)slot * d.model;
   float* E = a.E + (int64_t)slot * d.model;
+  const float* strip_base = a.strip + (int64_t)si.cs * a.strip_stride;
+  // resources: this slot's u levels and lam levels with the guard rows in
+  // front, w, g and E of the slot (E at a fixed offset after g), the strips
+  const rsrc_t rU = make_rsrc(ubase - d.guard, d.guard + a.ustride);
+  const rsrc_t rL = make_rsrc(lbase - d.guard, d.guard + a.lstride);
+  const rsrc_t rW = make_rsrc(a.w - CB, d.field + CB);
+  const rsrc_t rG = make_rsrc(G, (E - G) + d.model);
+  const rsrc_t rS = make_rsrc(strip_base, a.strip_stride);
+  // byte offset of row 0 of a level within rU / rL, less the column bias
+  auto lev = [&](int k) { return (int32_t)((d.guard + (int64_t)k * d.field - CB) * 4); };
+  const int32_t ouA0 = lev(uA0), ouA1 = lev(uA1), ouO0 = lev(uO0), ouO1 = lev(uO1);
+  const int32_t olA1 = lev(lA1), olA2 = lev(lA2), olO0 = lev(lO0), olO1 = lev(lO1);
+  const int32_t oE = (int32_t)((E - G) * 4);
+  const int32_t P4 = d.P * 4;
+
+  const bool hasSA = m >= 3, hasSB = m >= 4;  // strips of u[m-2], u[m-3] exist
+  const int32_t osA = hasSA ? (int32_t)((int64_t)(m - 2) * d.ring * 4) : 0;
+  const int32_t osB = hasSB ? (int32_t)((int64_t)(m - 3) * d.ring * 4) : 0;
+  const bool first = (m == sd.nt - 1);
 
   const bool src_tile = sd.src_z >= za0 && sd.src_z < za1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
+  const int src_row = src_tile ? sd.src_z : INT_MIN;
   const float fA = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 1)] : 0.0f;
   const float fB = (src_tile && hasB) ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 2)] : 0.0f;
 
-  // receiver rows of this tile, one cursor for each step
-  int rpA, rpB, rend;
+  // Bands of even zt sweep down (increasing z), odd ones up, so that two
+  // neighbouring bands read the rows they share at about the same time (the
+  // second read then comes from L2).  A visits its rows in sweep order, B
+  // follows 4 rows behind.
+  const int dz = (zt & 1) ? -1 : 1;
+  const int zA0 = dz > 0 ? za0 : za1 - 1;  // A's first row
+  const int nA = za1 - za0;
+
+  // receiver rows of this tile (sorted by z), one cursor for each step, in
+  // sweep order; INT_MAX once past the last
+  int rpA, rpB, rbeg, rend;
   {
     const RmapDir dir = a.rdir[sd.rdir2 + xt];
-    rpA = dir.begin;
+    rbeg = dir.begin;
     rend = dir.begin + dir.count;
-    while (rpA < rend && a.rrows[rpA].z < za0) ++rpA;
-    rpB = rpA;
-    while (rpB < rend && a.rrows[rpB].z < z0) ++rpB;
+    if (dz > 0) {
+      rpA = rbeg;
+      while (rpA < rend && a.rrows[rpA].z < za0) ++rpA;
+      rpB = rpA;
+      while (rpB < rend && a.rrows[rpB].z < z0) ++rpB;
+    } else {
+      rpA = rend - 1;
+      while (rpA >= rbeg && a.rrows[rpA].z >= za1) --rpA;
+      rpB = rpA;
+      while (rpB >= rbeg && a.rrows[rpB].z >= z1) --rpB;
+    }
   }
-  int rzA = rpA < rend ? a.rrows[rpA].z : INT_MAX;
-  int rzB = rpB < rend ? a.rrows[rpB].z : INT_MAX;
+  auto rz_at = [&](int rp) { return (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX; };
+  int rzA = rz_at(rpA);
+  int rzB = rz_at(rpB);
   const float* psiA = a.traces + (int64_t)m * a.ntrace;
   const float* psiB = a.traces + (int64_t)(m - 1) * a.ntrace;
 
-  const int uz_lo = d.N - kRadius, uz_hi = d.N + d.nz + kRadius;  // rows where u is defined
-  // A's inputs: u[m-1], lam[m+1] (stencil rings), their halo columns and u[m],
-  // lam[m+2], w (point-wise rings); B's per-row values in 5-row rings: w,
-  // A's g and E terms, the old g and E of owned rows
-  float uc[W], lc[W];
-  float uh[R], lh[R], p0[R], pl[R], pw[R];
-  float wr[W5], cg[W5], ce[W5], go[W5], eo[W5];
-  auto load_centre = [&](int r, float& cu, float& cl) {
-    cu = cl = 0.0f;
-    if (r >= 0 && r < d.Z && col.xin) {
-      const int64_t ro = (int64_t)r * d.P;
-      cl = lA1[ro + col.xs];
-      if (r >= uz_lo && r < uz_hi) {
-        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
-        cu = (mrow && col.mcol) ? snap1[(int64_t)(r - d.N) * d.nx + col.mx] : uA1[ro + col.xs];
-      }
-    }
-  };
-  auto load_pt = [&](int r, float& hu, float& hl, float& u0, float& l2, float& w) {
-    hu = hl = u0 = l2 = w = 0.0f;
-    if (r < 0 || r >= d.Z) return;
-    const int64_t ro = (int64_t)r * d.P;
-    if (col.hok) {
-      hl = lA1[ro + col.hcol];
-      if (r >= uz_lo && r < uz_hi) {
-        const bool mrow = reset && r >= d.N && r < d.N + d.nz;
-        hu = (mrow && hmcol) ? snap1[(int64_t)(r - d.N) * d.nx + hmx] : uA1[ro + col.hcol];
-      }
-    }
-    if (!col.xin) return;
-    const int64_t idx = ro + col.xs;
-    l2 = lA2[idx];
-    w = a.w[idx];
-    const int mz = r - d.N;
-    if (mz >= 0 && mz < d.nz && col.mcol)
-      u0 = reset ? snap0[(int64_t)mz * d.nx + col.mx] : uA0[idx];
-  };
-#pragma unroll
-  for (int j = 0; j < 8 + PF; ++j) load_centre(za0 - kRadius + j, uc[j], lc[j]);
-  load_pt(za0, uh[0], lh[0], p0[0], pl[0], pw[0]);
+  // per-lane byte offsets, fixed for the sweep
+  const uint32_t oc = (uint32_t)(col.xs + CB) * 4u;     // centre column
+  const uint32_t oh = (uint32_t)(col.hsafe + CB) * 4u;  // halo column (lanes 0..7)
+  const uint32_t om = (uint32_t)col.mxc * 4u;           // model column (clamped)
+  auto mrow4 = [&](int r) { return (int32_t)(min(max(r - d.N, 0), d.nz - 1) * d.nx * 4); };
+  // strip ring index of (row r, this lane) as a byte offset, 0 if none
+  auto strip_off = [&](int r) { return (uint32_t)max(strip_index(make_row(d, r), col), 0) * 4u; };
 
-  for (int zb = za0; zb < za1; zb += W) {
+  // rings indexed by sweep position p at slot (p + 4) % W
+  float uc[W], lc[W];         // A's inputs u[m-1], lam[m+1]: positions j-4 .. j+5
+  float uo[W], lo[W], dA[W];  // A's results u[m-2], lam[m], D of step m: positions j-9 .. j
+  float uh[R], lh[R], p0[R], pl[R], pw[R], sa[R];  // A's halo columns, point-wise operands, strip value
+  float wB[R], gB[R], eB[R], sb[R];                // B's point-wise operands, strip value
+  // every row issues the same loads (strip values: every row of a tile at
+  // the ring): stencil rows just outside the grid read the zero guard rows,
+  // point-wise rows are clamped into the grid (rows past it are never used)
+  auto load_win = [&](int r, float& cu, float& cl) {
+    cu = bld(rU, oc, ouA1 + r * P4);
+    cl = bld(rL, oc, olA1 + r * P4);
+  };
+  auto load_ptA = [&](int r, float& hu, float& hl, float& u0, float& l2, float& w, float& st) {
+    hu = bld(rU, oh, ouA1 + r * P4);
+    hl = bld(rL, oh, olA1 + r * P4);
+    const int rc = clamp_row(d, r);
+    u0 = bld(rU, oc, ouA0 + rc * P4);
+    l2 = bld(rL, oc, olA2 + rc * P4);
+    w = bld(rW, oc, rc * P4);
+    if (ring) st = bld(rS, strip_off(rc), osA);
+  };
+  auto load_ptB = [&](int r, float& w, float& g, float& e, float& st) {
+    const int rc = clamp_row(d, r);
+    const int32_t mo = mrow4(rc);
+    w = bld(rW, oc, rc * P4);
+    g = bld(rG, om, mo);
+    e = bld(rG, om, mo + oE);
+    if (ring) st = bld(rS, strip_off(rc), osB);
+  };
+  // sweep position j is row zA0 + dz j; the rings hold positions, and the
+  // stencil is symmetric in z, so both directions share the code
 #pragma unroll
-    for (int r = 0; r < W; ++r) {
-      const int z = zb + r;  // A's row; B's row is z - 4
-      if (z >= za1) break;
-      if (z + PF < za1) {
-        load_centre(z + kRadius + PF, uc[(r + 8 + PF) % W], lc[(r + 8 + PF) % W]);
+  for (int j = 0; j < 8 + PF; ++j) load_win(zA0 + dz * (j - kRadius), uc[j], lc[j]);
+#pragma unroll
+  for (int j = 0; j < R; ++j) sa[j] = sb[j] = 0.0f;
+  load_ptA(zA0, uh[0], lh[0], p0[0], pl[0], pw[0], sa[0]);
+  load_ptB(zA0 - dz * kRadius, wB[0], gB[0], eB[0], sb[0]);
+#pragma unroll
+  for (int j = 0; j < W; ++j) uo[j] = lo[j] = dA[j] = 0.0f;
+
+  for (int jb = 0; jb < nA; jb += W) {
+    static_for<W>([&](auto rc) __attribute__((always_inline)) {
+      constexpr int r = decltype(rc)::value;
+      const int j = jb + r;
+      if (j >= nA) return;
+      const int z = zA0 + dz * j;  // A's row; B's row is 4 rows behind
+      load_win(z + dz * (kRadius + PF), uc[(r + 8 + PF) % W], lc[(r + 8 + PF) % W]);
+      {
         const int qn = (r + PF) % R;
-        load_pt(z + PF, uh[qn], lh[qn], p0[qn], pl[qn], pw[qn]);
+        load_ptA(z + dz * PF, uh[qn], lh[qn], p0[qn], pl[qn], pw[qn], sa[qn]);
+        load_ptB(z - dz * (kRadius - PF), wB[qn], gB[qn], eB[qn], sb[qn]);
       }
       const int sA = (r + 4) % W;  // ring slot of row z
       const int sB = r % W;        // ring slot of row z - 4
-      const int tA = (r + 4) % W5, tB = r % W5;
+      const int qa = r % R;
+      // ---- the workgroup's rows: A's inputs at row z, A's results 4 rows behind
+      float(*xr)[LR] = xrow[r & 1];
+      xr[0][hidx] = uh[qa];
+      xr[0][cidx] = uc[sA];
+      xr[1][hidx] = lh[qa];
+      xr[1][cidx] = lc[sA];
+      xr[2][cidx] = uo[sB];
+      xr[3][cidx] = lo[sB];
+      // LDS-only release/acquire around the barrier: the loads in flight stay
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
       // ---- step A at row z (all 64 columns)
+      float lapL = laplace<W>(lc, r + 4, xr[1] + kWave * wv, lane);
+      float lapU = laplace<W>(uc, r + 4, xr[0] + kWave * wv, lane);
       {
-        const int qa = r % R;
-        const float cu = uc[sA], cl = lc[sA];
-        lds_put(ldsU, lane, cu, uh[qa]);
-        lds_put(ldsL, lane, cl, lh[qa]);
-        wave_lds_fence();
-        const bool inz = z >= 0 && z < d.Z;
-        const Row row = make_row(d, inz ? z : 0);
-        float lapL = laplace<W>(lc, r + 4, ldsL, lane);
-        float lapU = (inz && row.model) ? laplace<W>(uc, r + 4, ldsU, lane) : 0.0f;
-        if (z == rzA) {
-          const int tr = a.rmaps[a.rrows[rpA].map + lane];
-          if (tr >= 0) lapL += psiA[tr];
-          ++rpA;
-          rzA = rpA < rend ? a.rrows[rpA].z : INT_MAX;
-        }
-        if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lapU += fA;
-        const float w = pw[qa];
-        float lo = 0.0f, uo = 0.0f, tg = 0.0f, te = 0.0f;
-        if (inz && col.xin) {
+        const float w = pw[qa], cu = uc[sA], cl = lc[sA];
+        float lo_ = 0.0f, uo_ = 0.0f, d_ = 0.0f;
+        if (tile_int && z >= mz_lo && z < mz_hi && z != rzA && z != src_row) {
+          lo_ = fmaf(w, lapL, 2.0f * cl - pl[qa]);
+          d_ = w * lapU;
+          uo_ = fmaf(w, lapU, 2.0f * cu - p0[qa]);
+        } else if (z >= 0 && z < d.Z) {
+          if (z == rzA) {
+            const int tr = a.rmaps[a.rrows[rpA].map + lane];
+            if (tr >= 0) lapL += psiA[tr];
+            rpA += dz;
+            rzA = rz_at(rpA);
+          }
+          if (z == src_row && col.xs == sd.src_xs) lapU += fA;
+          const Row row = make_row(d, z);
           const int dd = max(row.dz, col.dxs);
-          lo = dd == 0 ? fmaf(w, lapL, 2.0f * cl - pl[qa]) : sponge_update(a.sp_a, dd, cl, pl[qa], w, lapL);
-          if (dd == 0) {
-            const float D = w * lapU;
-            uo = fmaf(w, lapU, 2.0f * cu - p0[qa]);
-            tg = lo * D;
-            te = D * D;
-          } else {
-            const int ri = strip_index(row, col);
-            if (ri >= 0) uo = stripA ? stripA[ri] : 0.0f;
+          if (col.xin && dd == 0) {
+            lo_ = fmaf(w, lapL, 2.0f * cl - pl[qa]);
+            d_ = w * lapU;
+            uo_ = fmaf(w, lapU, 2.0f * cu - p0[qa]);
+          } else if (col.xin) {
+            lo_ = sponge_update(a.sp_a, dd, cl, pl[qa], w, lapL);
+            if (hasSA && strip_index(row, col) >= 0) uo_ = sa[qa];
           }
         }
-        lds_put(ringU[sA], lane, uo, 0.0f);
-        lds_put(ringL[sA], lane, lo, 0.0f);
-        wr[tA] = w;
-        cg[tA] = tg;
-        ce[tA] = te;
-        go[tA] = 0.0f;
-        eo[tA] = 0.0f;
         if (z >= z0 && z < z1 && own_col) {
-          const int64_t idx = (int64_t)z * d.P + col.xs;
-          uO0[idx] = uo;
-          lO0[idx] = lo;
-          if (row.model && col.mcol) {
-            const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
-            go[tA] = G[mi];
-            eo[tA] = first ? 0.0f : E[mi];
-          }
+          bst(rU, oc, ouO0 + z * P4, uo_);
+          bst(rL, oc, olO0 + z * P4, lo_);
         }
+        uo[sA] = uo_;
+        lo[sA] = lo_;
+        dA[sA] = d_;
       }
-      wave_lds_fence();
-      // ---- step B at row z - 4 (owned lanes)
-      const int zbB = z - kRadius;
-      if (zbB >= z0 && zbB < z1) {
-        const Row row = make_row(d, zbB);
-        const float cu = ringU[sB][kRadius + lane], cl = ringL[sB][kRadius + lane];
-        // 8th-order Laplacian from the LDS rings: rows z-8 .. z, columns +-4
-        float lapU = 0.0f, lapL = 0.0f;
-#pragma unroll
-        for (int k = 4; k >= 1; --k) {
-          const int up = (r - k + W) % W, dn = (r + k) % W;
-          const float szL = ringL[up][kRadius + lane] + ringL[dn][kRadius + lane];
-          const float sxL = ringL[sB][kRadius + lane - k] + ringL[sB][kRadius + lane + k];
-          lapL = fmaf(ck(k), fmaf(-4.0f, cl, szL + sxL), lapL);
-          if (row.model) {
-            const float szU = ringU[up][kRadius + lane] + ringU[dn][kRadius + lane];
-            const float sxU = ringU[sB][kRadius + lane - k] + ringU[sB][kRadius + lane + k];
-            lapU = fmaf(ck(k), fmaf(-4.0f, cu, szU + sxU), lapU);
+      // ---- step B at row z - 4 dz (owned lanes), from sweep position 8 on
+      const int zbB = z - dz * kRadius;
+      if (j >= 2 * kRadius) {
+        const int qb = r % R;
+        float lapLB = laplace<W>(lo, r, xr[3] + kWave * wv, lane);
+        float lapUB = laplace<W>(uo, r, xr[2] + kWave * wv, lane);
+        const float w = wB[qb], cu = uo[sB], cl = lo[sB], pu = uc[sB], pl1 = lc[sB], da = dA[sB];
+        float l1 = 0.0f, u1 = 0.0f, gn = 0.0f, en = 0.0f;
+        bool st_l = own_col, st_u = own_col, st_g = own_col;
+        if (tile_int && zbB >= mz_lo && zbB < mz_hi && zbB != rzB && zbB != src_row && hasB) {
+          l1 = fmaf(w, lapLB, 2.0f * cl - pl1);
+          const float D = w * lapUB;
+          u1 = fmaf(w, lapUB, 2.0f * cu - pu);
+          gn = fmaf(l1, D, fmaf(cl, da, gB[qb]));
+          en = fmaf(D, D, fmaf(da, da, first ? 0.0f : eB[qb]));
+        } else {
+          if (zbB == rzB) {
+            const int tr = a.rmaps[a.rrows[rpB].map + lane];
+            if (tr >= 0 && hasB) lapLB += psiB[tr];
+            rpB += dz;
+            rzB = rz_at(rpB);
           }
-        }
-        if (zbB == rzB) {
-          const int tr = a.rmaps[a.rrows[rpB].map + lane];
-          if (tr >= 0 && hasB) lapL += psiB[tr];
-          ++rpB;
-          rzB = rpB < rend ? a.rrows[rpB].z : INT_MAX;
-        }
-        if (src_tile && zbB == sd.src_z && col.xs == sd.src_xs) lapU += fB;
-        if (own_col) {
-          const int64_t idx = (int64_t)zbB * d.P + col.xs;
+          if (zbB == src_row && col.xs == sd.src_xs) lapUB += fB;
+          const Row row = make_row(d, zbB);
           const int dd = max(row.dz, col.dxs);
-          const float w = wr[tB];
-          const float pu = uc[sB], pl1 = lc[sB];  // u[m-1], lam[m+1] at row z - 4
+          st_l = own_col && hasB;
+          st_g = own_col && dd == 0;
           if (dd == 0) {
-            const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
-            if (hasB) {
-              const float lo = fmaf(w, lapL, 2.0f * cl - pl1);
-              const float D = w * lapU;
-              lO1[idx] = lo;
-              uO1[idx] = fmaf(w, lapU, 2.0f * cu - pu);
-              G[mi] = fmaf(lo, D, go[tB] + cg[tB]);
-              E[mi] = fmaf(D, D, eo[tB] + ce[tB]);
-            } else {
-              G[mi] = go[tB] + cg[tB];
-              E[mi] = eo[tB] + ce[tB];
-            }
-          } else if (hasB) {
-            lO1[idx] = sponge_update(a.sp_a, dd, cl, pl1, w, lapL);
-            const int ri = strip_index(row, col);
-            if (ri >= 0) uO1[idx] = stripB ? stripB[ri] : 0.0f;
+            const float ag = fmaf(cl, da, gB[qb]);
+            const float ae = fmaf(da, da, first ? 0.0f : eB[qb]);
+            l1 = fmaf(w, lapLB, 2.0f * cl - pl1);
+            const float D = w * lapUB;
+            u1 = fmaf(w, lapUB, 2.0f * cu - pu);
+            gn = hasB ? fmaf(l1, D, ag) : ag;
+            en = hasB ? fmaf(D, D, ae) : ae;
+            st_u = st_l;
+          } else {
+            l1 = sponge_update(a.sp_a, dd, cl, pl1, w, lapLB);
+            u1 = hasSB ? sb[qb] : 0.0f;
+            st_u = st_l && strip_index(row, col) >= 0;
           }
         }
+        if (st_l) bst(rL, oc, olO1 + zbB * P4, l1);
+        if (st_u) bst(rU, oc, ouO1 + zbB * P4, u1);
+        if (st_g) {
+          const int32_t mo = mrow4(zbB);
+          bst(rG, om, mo, gn);
+          bst(rG, om, mo + oE, en);
+        }
       }
-      wave_lds_fence();
+    });
+  }
+
+  // the next launch restarts from snapshot k: its inputs u[m-2], u[m-3] take
+  // the snapshot's values in the model cells (after this wavefront's own
+  // stores of the reconstructed values, which only this launch used)
+  const int remn = sd.nt - 1 - (m - 2);
+  if (m - 2 >= 1 && (remn % sd.K) == 0 && remn / sd.K <= sd.nsnap) {
+    const float* sn0 = a.snap + (int64_t)si.cs * a.snap_stride + (int64_t)(remn / sd.K - 1) * 2 * d.model;
+    const float* sn1 = sn0 + d.model;
+    float* u0 = ubase + (int64_t)uO0 * d.field;
+    float* u1 = ubase + (int64_t)uO1 * d.field;
+    if (own_col && col.mcol) {
+      for (int z = max(z0, mz_lo); z < min(z1, mz_hi); ++z) {
+        const int64_t mi = (int64_t)(z - d.N) * d.nx + col.mx;
+        const int64_t idx = (int64_t)z * d.P + col.xs;
+        u0[idx] = sn0[mi];
+        u1[idx] = sn1[mi];
+      }
     }
   }
 }

@@ -280,7 +280,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->rev_steps = rev2 ? 2 : 1;
   p->ulevels = rev2 ? kULevels2 : kULevels;
   p->llevels = rev2 ? kLamLevels2 : kLamLevels;
-  p->XT2 = (d.X + kTile2 - 1) / kTile2;
+  p->XT2 = kWavesPerBlock * ((d.X + kBlk2 - 1) / kBlk2);
   const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
   p->sp_a = 0.5 * g->dt * eta_max / ((double)d.N * d.N);
 
@@ -334,16 +334,17 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   }
   if (p->rrows.empty()) p->rrows.push_back(RmapRow{0, 0});
   if (p->rmaps.empty()) p->rmaps.assign(kWave, -1);
-  // the same for the two-step tiling: tile t computes storage columns
-  // [off - 4 + 56 t, +64), so a receiver can sit in two tiles
+  // the same for the two-step tiling: wave tile t computes storage columns
+  // [tile2_x0(t), +64), and the workgroups' column ranges overlap by 8, so a
+  // receiver can sit in two tiles
   p->rdir2.assign((size_t)std::max(ns, 1) * std::max(p->XT2, 1), RmapDir{0, 0});
   if (rev2) {
     for (int s = 0; s < ns; ++s) {
       std::map<std::pair<int, int>, std::vector<int>> rows;  // (tile, z) -> traces
       for (int r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
-        const int rel = geo->rec_ix[r] + d.mx0 - (d.off - kRadius);  // >= 4
-        for (int t = std::max(0, (rel - kWave) / kTile2); t <= rel / kTile2 && t < p->XT2; ++t)
-          if (rel - kTile2 * t >= 0 && rel - kTile2 * t < kWave) rows[{t, geo->rec_iz[r] + d.N}].push_back(r);
+        const int c = geo->rec_ix[r] + d.mx0;
+        for (int t = 0; t < p->XT2; ++t)
+          if (c >= tile2_x0(d.off, t) && c < tile2_x0(d.off, t) + kWave) rows[{t, geo->rec_iz[r] + d.N}].push_back(r);
       }
       for (auto& kv : rows) {
         const int t = kv.first.first, z = kv.first.second;
@@ -353,8 +354,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
         const int map = (int)p->rmaps2.size();
         p->rrows2.push_back(RmapRow{z, map});
         p->rmaps2.resize(map + kWave, -1);
-        for (int r : kv.second)
-          p->rmaps2[map + (geo->rec_ix[r] + d.mx0 - (d.off - kRadius) - kTile2 * t)] = r;
+        for (int r : kv.second) p->rmaps2[map + (geo->rec_ix[r] + d.mx0 - tile2_x0(d.off, t))] = r;
       }
     }
   }
