@@ -183,7 +183,7 @@ hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
 // two reverse steps per launch (StepArgs::d.XT = two-step tiles, receiver
 // maps of that tiling, step = launch index); no extended image, eq. (3) or
 // free surface
-hipError_t launch_reverse2(const StepArgs& a, hipStream_t s);
+hipError_t launch_reverse2(const StepArgs& a, int prefetch, hipStream_t s);
 hipError_t launch_ext_out(const Dims& d, const float* Iacc, int groups, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);

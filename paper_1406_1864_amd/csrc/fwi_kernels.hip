@@ -622,10 +622,14 @@ __device__ __forceinline__ void lds_put_nb(float* lds, int hidx, int lane, float
   lds[kRadius + lane] = c;
 }
 
-__global__ __launch_bounds__(256) void k_reverse2(StepArgs a) {
-  constexpr int PF = 1;      // rows of loads in flight ahead of A
-  constexpr int W = 10;      // register rings: the unrolled period
-  constexpr int R = PF + 1;  // point-wise rings
+// (at least 4 wavefronts per SIMD: the compiler keeps the deeper prefetch
+// within 128 VGPRs)
+template <int PF>
+__global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
+  // PF: rows of loads in flight ahead of A (1 or 3)
+  constexpr int W = PF == 1 ? 10 : 12;  // register rings: the unrolled period
+  constexpr int R = PF + 1;             // point-wise rings
+  static_assert(W >= 9 + PF && W % R == 0, "ring lengths must fit the window and the unrolled period");
   constexpr int LR = kWavesPerBlock * kWave + 2 * kRadius;
   constexpr int CB = 2 * kRadius;  // column bias of the lane offsets (halo columns reach -4)
   // the workgroup's rows of A's inputs (u, lam) and of A's results (for B),
@@ -783,8 +787,11 @@ __global__ __launch_bounds__(256) void k_reverse2(StepArgs a) {
   for (int j = 0; j < 8 + PF; ++j) load_win(zA0 + dz * (j - kRadius), uc[j], lc[j]);
 #pragma unroll
   for (int j = 0; j < R; ++j) sa[j] = sb[j] = 0.0f;
-  load_ptA(zA0, uh[0], lh[0], p0[0], pl[0], pw[0], sa[0]);
-  load_ptB(zA0 - dz * kRadius, wB[0], gB[0], eB[0], sb[0]);
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    load_ptA(zA0 + dz * j, uh[j], lh[j], p0[j], pl[j], pw[j], sa[j]);
+    load_ptB(zA0 - dz * (kRadius - j), wB[j], gB[j], eB[j], sb[j]);
+  }
 #pragma unroll
   for (int j = 0; j < W; ++j) uo[j] = lo[j] = dA[j] = 0.0f;
 
@@ -1403,8 +1410,10 @@ hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_reverse2(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reverse2, dim3(step_blocks(a.d, a.S)), dim3(256), 0, s, a);
+hipError_t launch_reverse2(const StepArgs& a, int prefetch, hipStream_t s) {
+  const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  if (prefetch == 3) hipLaunchKernelGGL(k_reverse2<3>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_reverse2<1>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -535,7 +535,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   if (ext && p.ext_h < 0) return fail(FWI_ERR_STATE, "extended image without its buffers");
   ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
-    if (two) return launch_reverse2(args, s);
+    if (two) return launch_reverse2(args, p.pf_rev, s);
     return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
                               : launch_reverse(args, p.pf_rev, flags, s);
   };
@@ -818,8 +818,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
         double rb = 1e30;
         int rpf = RFs[0], rrs = RSs[0];
         for (int rs : RSs) {
-          // the two-step sweep has one prefetch depth of its own
-          for (int pf : (rs == 2 ? std::vector<int>{RFs[0]} : RFs)) {
+          for (int pf : RFs) {
             p->rev_steps = rs;
             p->pf_rev = pf;
             const double ms = timed(*p, 0, kPhaseRev);

@@ -29,10 +29,11 @@ EXECS = {
     # the reverse sweep takes each forward batch two shots at a time, 8-row tiles
     "split_config": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=16, tile_rows_reverse=8,
                                 graph_steps=5),
-    # two reverse steps per launch, direct launches and graph chunks
+    # two reverse steps per launch, direct launches and graph chunks (the
+    # latter with loads three rows ahead)
     "two_step": B.make_exec(shots_in_flight=3, tile_rows=16, graph_steps=-1, reverse_steps=2),
     "two_step_graph": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=24, tile_rows_reverse=12,
-                                  graph_steps=5, reverse_steps=2),
+                                  graph_steps=5, reverse_steps=2, prefetch_reverse=3),
 }
 
 
