@@ -240,13 +240,25 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
   const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + n] : 0.0f;
 
-  int rp = 0, rend = 0, rz = INT_MAX;
+  // tiles of even zt sweep down (increasing z), odd ones up: two vertically
+  // neighbouring tiles then read the rows they share at about the same time
+  // (the second read comes from L2); the top tile of a free-surface grid
+  // (zt = 0) always sweeps down
+  const int dz = (zt & 1) ? -1 : 1;
+  const int zS = dz > 0 ? z0 : z1 - 1, nT = z1 - z0;
+  int rp = 0, rbeg = 0, rend = 0, rz = INT_MAX;
   if (FLAGS & kFwdRecord) {
     const RmapDir dir = a.rdir[sd.rdir + xt];
-    rp = dir.begin;
+    rbeg = dir.begin;
     rend = dir.begin + dir.count;
-    while (rp < rend && a.rrows[rp].z < z0) ++rp;
-    rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+    if (dz > 0) {
+      rp = rbeg;
+      while (rp < rend && a.rrows[rp].z < z0) ++rp;
+    } else {
+      rp = rend - 1;
+      while (rp >= rbeg && a.rrows[rp].z >= z1) --rp;
+    }
+    rz = (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX;
   }
   // snapshot pair k holds (u[a_k], u[a_k - 1]) with a_k = nt-1-kK, k >= 1
   bool save = false;
@@ -307,29 +319,32 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
   } else {
 #pragma unroll
     for (int j = 0; j < 8 + PF; ++j) {
-      load_row(z0 - 4 + j, wc[j], wh[j]);
-      if (BORN) load_brow(z0 - 4 + j, bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
+      load_row(zS + dz * (j - 4), wc[j], wh[j]);
+      if (BORN) load_brow(zS + dz * (j - 4), bc[j % (BORN ? W : 1)], bh[j % (BORN ? W : 1)]);
     }
   }
 #pragma unroll
   for (int j = 0; j < PF; ++j) {
-    load_pt(z0 + j, pd[j], pw[j]);
-    if (BORN) load_bpt(z0 + j, pbd[j % (BORN ? R : 1)], pbw[j % (BORN ? R : 1)]);
+    load_pt(zS + dz * j, pd[j], pw[j]);
+    if (BORN) load_bpt(zS + dz * j, pbd[j % (BORN ? R : 1)], pbw[j % (BORN ? R : 1)]);
   }
 
-  for (int zb = z0; zb < z1; zb += W) {
+  // sweep position j is row zS + dz j; the rings hold positions, and the
+  // stencil is symmetric in z
+  for (int jb = 0; jb < nT; jb += W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
-      const int z = zb + r;
-      if (z >= z1) break;
+      const int j = jb + r;
+      if (j >= nT) break;
+      const int z = zS + dz * j;
       // the next rows' loads are issued on every row, also past the tile
       // (clamped into the grid): with the same loads on every path the
       // compiler waits only for the rows consumed now
-      load_row(z + 4 + PF, wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
-      load_pt(z + PF, pd[(r + PF) % R], pw[(r + PF) % R]);
+      load_row(z + dz * (4 + PF), wc[(r + 8 + PF) % W], wh[(r + 8 + PF) % W]);
+      load_pt(z + dz * PF, pd[(r + PF) % R], pw[(r + PF) % R]);
       if (BORN) {
-        load_brow(z + 4 + PF, bc[(r + 8 + PF) % (BORN ? W : 1)], bh[(r + 8 + PF) % (BORN ? W : 1)]);
-        load_bpt(z + PF, pbd[(r + PF) % (BORN ? R : 1)], pbw[(r + PF) % (BORN ? R : 1)]);
+        load_brow(z + dz * (4 + PF), bc[(r + 8 + PF) % (BORN ? W : 1)], bh[(r + 8 + PF) % (BORN ? W : 1)]);
+        load_bpt(z + dz * PF, pbd[(r + PF) % (BORN ? R : 1)], pbw[(r + PF) % (BORN ? R : 1)]);
       }
       const float c = wc[(r + 4) % W];
       lds_put(lds, lane, c, wh[(r + 4) % W]);
@@ -390,8 +405,8 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
         if (z == rz) {
           const int tr = a.rmaps[a.rrows[rp].map + lane];
           if (tr >= 0) a.traces[(int64_t)(n + 1) * a.ntrace + tr] = BORN ? bout : out;
-          ++rp;
-          rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+          rp += dz;
+          rz = (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX;
         }
       }
     }
@@ -462,14 +477,25 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
   const bool src_tile = sd.src_z >= z0 && sd.src_z < z1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
   const float fsrc = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + (m - 1)] : 0.0f;
 
-  int rp, rend, rz;
+  // tiles of even zt sweep down (increasing z), odd ones up: two vertically
+  // neighbouring tiles then read the rows they share at about the same time
+  // (the second read comes from L2)
+  const int dz = (zt & 1) ? -1 : 1;
+  const int zS = dz > 0 ? z0 : z1 - 1, nT = z1 - z0;
+  int rp, rbeg, rend;
   {
     const RmapDir dir = a.rdir[sd.rdir + xt];
-    rp = dir.begin;
+    rbeg = dir.begin;
     rend = dir.begin + dir.count;
-    while (rp < rend && a.rrows[rp].z < z0) ++rp;
-    rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+    if (dz > 0) {
+      rp = rbeg;
+      while (rp < rend && a.rrows[rp].z < z0) ++rp;
+    } else {
+      rp = rend - 1;
+      while (rp >= rbeg && a.rrows[rp].z >= z1) --rp;
+    }
   }
+  int rz = (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX;
   const float* psi = a.traces + (int64_t)m * a.ntrace;
 
   float uc[W], uh[W], lc[W], lh[W];
@@ -514,20 +540,23 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < 8 + PF; ++j) load_rows(z0 - 4 + j, uc[j], uh[j], lc[j], lh[j]);
+    for (int j = 0; j < 8 + PF; ++j) load_rows(zS + dz * (j - 4), uc[j], uh[j], lc[j], lh[j]);
   }
 #pragma unroll
-  for (int j = 0; j < PF; ++j) load_pt(z0 + j, p0[j], pl[j], pw[j], pg[j], pe[j]);
+  for (int j = 0; j < PF; ++j) load_pt(zS + dz * j, p0[j], pl[j], pw[j], pg[j], pe[j]);
 
-  for (int zb = z0; zb < z1; zb += W) {
+  // sweep position j is row zS + dz j; the rings hold positions, and the
+  // stencil is symmetric in z
+  for (int jb = 0; jb < nT; jb += W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
-      const int z = zb + r;
-      if (z >= z1) break;
+      const int j = jb + r;
+      if (j >= nT) break;
+      const int z = zS + dz * j;
       {
         const int s = (r + 8 + PF) % W, q = (r + PF) % R;
-        load_rows(z + 4 + PF, uc[s], uh[s], lc[s], lh[s]);
-        load_pt(z + PF, p0[q], pl[q], pw[q], pg[q], pe[q]);
+        load_rows(z + dz * (4 + PF), uc[s], uh[s], lc[s], lh[s]);
+        load_pt(z + dz * PF, p0[q], pl[q], pw[q], pg[q], pe[q]);
       }
       const int ctr = (r + 4) % W;
       const float cu = uc[ctr], cl = lc[ctr];
@@ -542,8 +571,8 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
       if (z == rz) {
         const int tr = a.rmaps[a.rrows[rp].map + lane];
         if (tr >= 0) lapL += psi[tr];
-        ++rp;
-        rz = rp < rend ? a.rrows[rp].z : INT_MAX;
+        rp += dz;
+        rz = (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX;
       }
       float lapU = lapU0;
       if (src_tile && z == sd.src_z && col.xs == sd.src_xs) lapU += fsrc;
