@@ -131,10 +131,11 @@ typedef struct {
                                  tuned, or tile_rows                           */
     int32_t reverse_steps;    /* time steps per launch of the adjoint sweep of
                                  fwi_gradient / fwi_misfit_backward /
-                                 fwi_gn_hvp: 1, or 2 (temporal blocking: the
-                                 first step on 64 columns, the second on the 56
-                                 inside, one read and one write of every field
-                                 for both); 0 = tuned, else 1.  Two steps are
+                                 fwi_gn_hvp: 1, or 2 (temporal blocking: a
+                                 workgroup computes the first step on 256
+                                 columns and the second on the 248 inside, one
+                                 read and one write of every field for both);
+                                 0 = tuned, else 1.  Two steps are
                                  not used with a free surface, in plain mode or
                                  for the extended image / eq. (3) variants     */
 } fwi_exec;

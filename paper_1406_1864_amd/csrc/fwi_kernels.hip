@@ -643,14 +643,6 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, 0);
 }
 
-// LDS row exchange without lane tests: lanes 0..7 write their halo value to
-// its slot, the other lanes to their own slot, which the centre value then
-// overwrites (LDS operations of one wavefront complete in order)
-__device__ __forceinline__ void lds_put_nb(float* lds, int hidx, int lane, float c, float h) {
-  lds[hidx] = h;
-  lds[kRadius + lane] = c;
-}
-
 // (at least 4 wavefronts per SIMD: the compiler keeps the deeper prefetch
 // within 128 VGPRs)
 template <int PF>
