@@ -66,11 +66,12 @@ def test_layered_1024x384_short_record(S, TZ):
           np.repeat(both, rs, axis=0), mult=4.0)
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "two_step"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "two_step", "two_step_pf3"])
 def test_layered_1024x384_full_record(mode):
     z, w, grid, geom, wav, d_obs = golden("layered_1024x384_nt4000")
     ex = {"plain": B.make_exec(mode=B.EXEC_PLAIN), "batched": B.make_exec(autotune=1),
-          "two_step": B.make_exec(reverse_steps=2, tile_rows_reverse=16)}[mode]
+          "two_step": B.make_exec(reverse_steps=2, tile_rows_reverse=16),
+          "two_step_pf3": B.make_exec(reverse_steps=2, tile_rows_reverse=32, prefetch_reverse=3)}[mode]
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
     check(f"layered nt4000 {mode}", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr)
