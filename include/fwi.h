@@ -125,7 +125,11 @@ typedef struct {
     int32_t shots_in_flight_reverse; /* shots per launch of the reverse sweep;
                                  it takes each forward batch's shots this many
                                  at a time, so it must divide shots_in_flight
-                                 (else the forward's value is used);
+                                 (else the forward's value is used); for the
+                                 autograd pair fwi_misfit_forward/backward,
+                                 which keeps every shot's checkpoints, any
+                                 value up to the number of shots (the shots,
+                                 longest records first, this many at a time);
                                  0 = tuned, or the forward's                   */
     int32_t tile_rows_reverse; /* rows per tile of the reverse sweep; 0 =
                                  tuned, or tile_rows                           */

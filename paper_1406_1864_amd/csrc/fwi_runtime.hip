@@ -226,6 +226,17 @@ int default_shots_in_flight(int nshot) {
   return std::max(S, 1);
 }
 
+// Shots per reverse launch: requested (else the forward's).  Where the reverse
+// sweep follows each forward batch it takes that batch's shots a divisor at a
+// time; in the autograd split (all checkpoints kept) any group size up to the
+// number of shots.
+int resolve_sr(int S, int req, int plain, bool split, int nshot) {
+  if (plain || req <= 0) return S;
+  if (split) return std::max(1, std::min(req, std::max(nshot, 1)));
+  const int Sr = std::max(1, std::min(req, S));
+  return S % Sr ? S : Sr;
+}
+
 void build_dims(Plan& p, const fwi_grid* g, int TZ) {
   Dims& d = p.d;
   d.nz = g->nz;
@@ -262,8 +273,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->dx = g->dx;
   p->dt = g->dt;
   p->S = plain ? 1 : std::max(1, std::min(ex.S, std::max(geo->nshot, 1)));
-  p->Sr = (plain || ex.Sr <= 0) ? p->S : std::max(1, std::min(ex.Sr, p->S));
-  if (p->S % p->Sr) p->Sr = p->S;  // validated by the caller; keep the tables consistent
+  p->Sr = resolve_sr(p->S, ex.Sr, plain, p->split, geo->nshot);
   p->graph_steps = plain ? -1 : ex.graph_steps;
   p->xcd_map = (p->S >= 8 && p->S % 8 == 0) ? 1 : 0;
   p->xcd_map_r = (p->Sr >= 8 && p->Sr % 8 == 0) ? 1 : 0;
@@ -375,7 +385,23 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   }
   p->ncs = p->split ? std::max(ns, 1) : p->S;
   p->rbatch_begin.assign(p->nbatch + 1, 0);
-  for (int b = 0; b < p->nbatch; ++b) {
+  if (p->split) {
+    // every shot keeps its checkpoints until the reverse sweep, which runs
+    // after all forward batches: it groups the shots (longest records first)
+    // Sr at a time, independently of the forward batches
+    for (int i0 = 0; i0 < ns; i0 += p->Sr) {
+      int nt = 0;
+      for (int k = 0; k < p->Sr; ++k) {
+        const SlotInfo si = i0 + k < ns ? SlotInfo{order[i0 + k], order[i0 + k]} : SlotInfo{-1, 0};
+        p->rslots.push_back(si);
+        if (si.shot >= 0) nt = std::max(nt, p->shots[si.shot].nt);
+      }
+      p->rbatch_nt.push_back(nt);
+    }
+    // (a whole-gradient call would run them all after the last forward batch)
+    p->rbatch_begin[p->nbatch] = (int)p->rbatch_nt.size();
+  }
+  for (int b = 0; b < p->nbatch && !p->split; ++b) {
     p->rbatch_begin[b] = (int)p->rbatch_nt.size();
     for (int j = 0; j < p->S; j += p->Sr) {
       int nt = 0;
@@ -391,7 +417,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
       p->rbatch_nt.push_back(nt);
     }
   }
-  p->rbatch_begin[p->nbatch] = (int)p->rbatch_nt.size();
+  if (!p->split) p->rbatch_begin[p->nbatch] = (int)p->rbatch_nt.size();
   p->nrbatch = (int)p->rbatch_nt.size();
   if (p->rslots.empty()) p->rslots.assign(p->Sr, SlotInfo{-1, 0});
 
@@ -774,7 +800,9 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
                      what == FWI_WS_GNHVP);
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
-  const int nsteps = 16;
+  const int nsteps = 32;
+  // FWI_TUNE_LOG set: each candidate's best time goes to stderr
+  const bool tune_log = getenv("FWI_TUNE_LOG") != nullptr;
   // best of two timings of `nsteps` launches, to keep the choice stable
   auto timed = [&](Plan& p, int flags, int phase) {
     return std::min(time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s),
@@ -813,6 +841,8 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
           if (ms < fb * 0.98) { fb = ms; fpf = pf; }
         }
         F.push_back(Cand{S, TZ, fpf, 1, fb / shots});
+        if (tune_log) fprintf(stderr, "[fwi tune] forward S %d TZ %d PF %d: %.3f us per shot-step\n", S, TZ, fpf,
+                              1e3 * fb / shots / nsteps);
       }
       if (tr) {
         double rb = 1e30;
@@ -826,12 +856,16 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
           }
         }
         Rv.push_back(Cand{S, TZ, rpf, rrs, rb / shots});
+        if (tune_log)
+          fprintf(stderr, "[fwi tune] reverse S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, rpf, rrs,
+                  1e3 * rb / shots / nsteps);
       }
     }
   }
   if (F.empty()) return FWI_OK;  // nothing fitted the workspace: keep the defaults
   // the pair with the least time per shot, the reverse's shots in flight
-  // dividing the forward's; a later pair must be 2 % faster to replace one
+  // dividing the forward's (any size in the autograd split); a later pair
+  // must be 2 % faster to replace one
   double best_t = 1e300;
   ExecChoice choice = best;
   for (const Cand& f : F) {
@@ -843,7 +877,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       continue;
     }
     for (const Cand& r : Rv) {
-      if (r.S > f.S || f.S % r.S) continue;
+      if (what != FWI_WS_AUTOGRAD && (r.S > f.S || f.S % r.S)) continue;
       const double t = f.per_shot + r.per_shot;
       if (t < best_t * 0.98) {
         best_t = t;
@@ -937,7 +971,7 @@ bool cache_lookup(const std::vector<uint64_t>& k, ExecChoice& c) {
     if (sscanf(colon + 1, "%d %d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
                &t.TZr, &t.rsteps) == 8 &&
         (t.rsteps == 1 || t.rsteps == 2) &&
-        t.Sr > 0 && t.S % t.Sr == 0 && t.TZr >= 8 && t.TZr <= 4096 &&
+        t.Sr > 0 && t.TZr >= 8 && t.TZr <= 4096 &&
         t.S > 0 && t.TZ >= 8 && t.TZ <= 4096 && (t.graph_steps == -1 || (t.graph_steps > 0 && t.graph_steps <= 1024)) &&
         (t.pf_fwd == 1 || t.pf_fwd == 3 || t.pf_fwd == 7) &&
         (t.pf_rev == 1 || t.pf_rev == 3)) {
@@ -1106,10 +1140,8 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
   chosen->prefetch_reverse = c.pf_rev;
   {
     // the reverse sweep's settings as build_plan resolves them
-    const int S = chosen->shots_in_flight;
-    int Sr = (plain || c.Sr <= 0) ? S : std::max(1, std::min(c.Sr, S));
-    if (S % Sr) Sr = S;
-    chosen->shots_in_flight_reverse = Sr;
+    chosen->shots_in_flight_reverse =
+        resolve_sr(chosen->shots_in_flight, c.Sr, plain, what == FWI_WS_AUTOGRAD, geom->nshot);
     chosen->tile_rows_reverse = c.TZr > 0 ? c.TZr : c.TZ;
     chosen->reverse_steps = (plain || grid->free_surface) ? 1 : c.rsteps;
   }

@@ -159,7 +159,8 @@ def test_eq3_literal_is_gradient_only(lib):
 
 def test_reverse_launch_settings(lib):
     """The reverse sweep's shots in flight must divide the forward's, else the
-    forward's value is used; its tile rows default to the forward's."""
+    forward's value is used (the autograd pair: any value up to the number of
+    shots); its tile rows default to the forward's."""
     w = layered_1024x384(nshot=8)
     q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=8, shots_in_flight_reverse=4,
                                                      tile_rows=32, tile_rows_reverse=12), B.WS_GRADIENT)
@@ -169,6 +170,15 @@ def test_reverse_launch_settings(lib):
     assert q["shots_in_flight_reverse"] == 8
     q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=8, tile_rows=16), B.WS_GRADIENT)
     assert q["tile_rows_reverse"] == 16
+    # the autograd pair keeps every shot's checkpoints: its reverse sweep groups
+    # the shots on its own, up to all of them, whatever the forward batch
+    for what, want in ((B.WS_AUTOGRAD, 8), (B.WS_GRADIENT, 2)):
+        q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=8), what)
+        assert q["shots_in_flight_reverse"] == want
+    q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=3), B.WS_AUTOGRAD)
+    assert q["shots_in_flight_reverse"] == 3
+    q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=99), B.WS_AUTOGRAD)
+    assert q["shots_in_flight_reverse"] == 8
     g, geo = _tiny()
     with pytest.raises(B.FwiError) as e:
         B.fwi_exec_query(g, geo, B.make_exec(tile_rows_reverse=4), B.WS_GRADIENT)

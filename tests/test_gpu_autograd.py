@@ -42,6 +42,28 @@ def test_autograd_matches_oracle(anomaly, exec_):
     assert report("autograd D", rel(pr.offset.cpu().numpy(), Dref), GRAD_TOL) < GRAD_TOL
 
 
+@pytest.mark.parametrize("exec_", [
+    B.make_exec(shots_in_flight=1, shots_in_flight_reverse=3, reverse_steps=2, graph_steps=5),
+    B.make_exec(shots_in_flight=2, shots_in_flight_reverse=4, tile_rows_reverse=8, graph_steps=-1)])
+def test_autograd_ragged_reverse_groups(exec_):
+    """The autograd pair keeps every shot's checkpoints, so its reverse sweep
+    groups the shots on its own: groups larger than the forward batches, the
+    last one partly idle, uneven record lengths (5 shots)."""
+    from test_gpu_parity import ragged_geometry
+    grid, geom, v_true, v_start, wav = ragged_geometry()
+    d_obs = oracle.forward_traces(v_true, grid, geom, wav)
+    J, g, H1 = oracle.gradient(v_start, grid, geom, wav, d_obs, "int")
+    pr = FWIProblem(grid, geom, wav, d_obs.astype(np.float32), "int", exec_)
+    v = torch.tensor(v_start, device="cuda", requires_grad=True)
+    Jg = fwi_misfit(v, pr)
+    Jg.backward()
+    syn = oracle.forward_traces(v_start, grid, geom, wav)
+    jt = j_tolerance(syn, d_obs, "int", grid.dt)
+    assert report("autograd ragged groups J", abs(float(Jg) - J) / J, jt) <= jt
+    assert report("autograd ragged groups grad", rel(v.grad.cpu().numpy(), g), GRAD_TOL) < GRAD_TOL
+    assert report("autograd ragged groups H1", rel(pr.illum.cpu().numpy(), H1), GRAD_TOL) < GRAD_TOL
+
+
 def test_autograd_equals_fused_gradient(anomaly):
     """The split forward/backward and the fused fwi_gradient give the same
     numbers (same kernels, same order)."""
