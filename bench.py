@@ -298,15 +298,14 @@ def main():
     rev_bytes = float(sum((nt[s] - 1) * reverse_bytes_per_shot_step(grid, int(nrec[s])) for s in range(shots)))
     rev_ms = phase[1] / args.steps
     chosen = B.fwi_exec_query(grid, pr.geom, ex, B.WS_AUTOGRAD)
-    # k_reverse launches per backward: the forward runs shots in batches of
-    # `shots_in_flight` (longest records first), the reverse takes each batch
-    # `shots_in_flight_reverse` at a time, each group for its longest record
-    S = max(1, chosen["shots_in_flight"])
+    # reverse launches per backward: the autograd pair keeps every shot's
+    # checkpoints, and its reverse sweep takes the shots (longest records
+    # first) `shots_in_flight_reverse` at a time, each group for its longest
+    # record, `reverse_steps` time steps per launch
     Sr = max(1, chosen["shots_in_flight_reverse"])
     order = sorted(range(shots), key=lambda s: -int(nt[s]))
     RS = max(1, chosen["reverse_steps"])
-    launches = sum((int(nt[order[b + j]]) - 1 + RS - 1) // RS for b in range(0, shots, S) for j in range(0, S, Sr)
-                   if b + j < shots)
+    launches = sum((int(nt[order[i0]]) - 1 + RS - 1) // RS for i0 in range(0, shots, Sr))
     launch_us = rev_ms * 1e3 / max(launches, 1)
     bytes_per_launch = rev_bytes / max(launches, 1)
     achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
