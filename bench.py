@@ -313,7 +313,9 @@ def main():
     fwd_bytes = float(sum((nt[s] - 1) * forward_bytes_per_shot_step(grid, int(nrec[s]), fwd_K)
                           for s in range(shots)))
     full = (shots == full_shots and not args.nt)
-    traffic = measured_traffic("k_reverse", chosen) if (args.workload == "layered" and full) else None
+    # the dominant kernel: the one-step or the two-step reverse sweep
+    rev_kernel = "k_reverse2" if RS == 2 else "k_reverse"
+    traffic = measured_traffic(rev_kernel, chosen) if (args.workload == "layered" and full) else None
     nrec_mean = float(np.mean(nrec)) if shots else 0.0
     out = {
         "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
@@ -341,7 +343,7 @@ def main():
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},
-        "roofline": {"bound": "hbm", "kernel": "k_reverse", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": rev_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches,
                      "avg_launch_us": launch_us},

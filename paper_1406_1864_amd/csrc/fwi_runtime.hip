@@ -863,6 +863,13 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     }
   }
   if (F.empty()) return FWI_OK;  // nothing fitted the workspace: keep the defaults
+  // near-ties (within the 2 % below) go to the reverse settings that move the
+  // fewest bytes per step: two steps per launch, then more shots per launch.
+  // A short timing flatters the one-step sweep: it leaves out the slower
+  // restart launches, and its small working set reuses the previous launch's
+  // fields from the Infinity Cache more than over a whole sweep.
+  std::stable_sort(Rv.begin(), Rv.end(),
+                   [](const Cand& x, const Cand& y) { return x.rs > y.rs || (x.rs == y.rs && x.S > y.S); });
   // the pair with the least time per shot, the reverse's shots in flight
   // dividing the forward's (any size in the autograd split); a later pair
   // must be 2 % faster to replace one
