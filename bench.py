@@ -58,7 +58,7 @@ def parse():
                     help="also time the Gauss-Newton Hessian-vector product against the plain gradient call")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
-                         "S,TZ,graph_steps,prefetch,prefetch_reverse")
+                         "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps]")
     return ap.parse_args()
 
 
@@ -106,7 +106,7 @@ def measured_traffic(kname, chosen):
     if p.get("kernel_source_sha") != kernel_hash():
         return None
     keys = ("shots_in_flight", "tile_rows", "graph_steps", "prefetch", "prefetch_reverse",
-            "shots_in_flight_reverse", "tile_rows_reverse", "reverse_steps")
+            "shots_in_flight_reverse", "tile_rows_reverse", "reverse_steps", "forward_steps")
     if any(p["launch_config"].get(k) != chosen.get(k) for k in keys):
         return None
     return p.get("bytes_per_launch")
@@ -240,9 +240,9 @@ def main():
     if args.exec:
         vals = [int(x) for x in args.exec.split(",")]
         S_, TZ_, G_, PF_, PR_ = vals[:5]
-        SR_, TZR_, RS_ = (vals[5:8] + [0, 0, 0])[:3]
+        SR_, TZR_, RS_, FS_ = (vals[5:9] + [0, 0, 0, 0])[:4]
         ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_,
-                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_, reverse_steps=RS_)
+                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_, reverse_steps=RS_, forward_steps=FS_)
     else:
         ex = B.make_exec(autotune=1)
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
@@ -339,7 +339,7 @@ def main():
                    "prefetch_reverse": chosen["prefetch_reverse"],
                    "shots_in_flight_reverse": chosen["shots_in_flight_reverse"],
                    "tile_rows_reverse": chosen["tile_rows_reverse"],
-                   "reverse_steps": chosen["reverse_steps"]},
+                   "reverse_steps": chosen["reverse_steps"], "forward_steps": chosen["forward_steps"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},

@@ -142,6 +142,14 @@ typedef struct {
                                  0 = tuned, else 1.  Two steps are
                                  not used with a free surface, in plain mode or
                                  for the extended image / eq. (3) variants     */
+    int32_t forward_steps;    /* time steps per launch of the forward sweep
+                                 of fwi_gradient / fwi_misfit_forward /
+                                 fwi_extended_image: 1, or 2 (the same
+                                 workgroup tiling; u[n+1], u[n+2], d[n+2]
+                                 written once per two steps); 0 = tuned, else
+                                 1.  Not used with a free surface, in plain
+                                 mode, for Born modelling or the forward-only
+                                 calls                                         */
 } fwi_exec;
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };

@@ -184,6 +184,11 @@ hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
 // maps of that tiling, step = launch index); no extended image, eq. (3) or
 // free surface
 hipError_t launch_reverse2(const StepArgs& a, int prefetch, hipStream_t s);
+hipError_t launch_forward2(const StepArgs& a, int prefetch, hipStream_t s);
+// after a two-step forward sweep: shots whose final state sits in the second
+// set of u levels (an odd number of launches) get it copied to the first
+hipError_t launch_forward2_finish(float* u, int64_t ustride, int64_t set_floats, const SlotInfo* slots,
+                                  const ShotDesc* shots, int S, hipStream_t s);
 hipError_t launch_ext_out(const Dims& d, const float* Iacc, int groups, int hmax, const float* v, float* image,
                           const int32_t* err, hipStream_t s);
 hipError_t launch_advance(int32_t* ctr, int32_t by, hipStream_t s);

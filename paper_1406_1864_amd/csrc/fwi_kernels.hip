@@ -954,6 +954,248 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
 }
 
 // -------------------------------------------------------------------------
+// Two forward steps per launch for the gradient's forward sweep (recording,
+// checkpoints; no free surface), A = step n -> n+1 and B = step n+1 -> n+2,
+// with the workgroup tiling of the two-step reverse sweep: A on 256 columns,
+// B on the 248 inside them, rows exchanged through LDS with one barrier per
+// row, A 4 rows ahead of B and over 4 more rows on either side of the band,
+// A's results u[n+1], d[n+1] of the last 10 (12) rows in register rings.
+// The u levels hold two sets of (u[k] at k & 1, d) in levels 0-2 and 3-5: a
+// launch reads one set and writes u[n+1], u[n+2], d[n+2] into the other
+// (neighbouring workgroups read the inputs in their overlap).  A shot whose
+// last launch ends after A (an odd number of steps) stores u[n], u[n+1],
+// d[n+1] instead.  Strips, snapshots and traces are written by the step
+// that produces them, as in the one-step sweep.
+// -------------------------------------------------------------------------
+template <int PF>
+__global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
+  constexpr int W = PF == 1 ? 10 : 12;  // register rings: the unrolled period
+  constexpr int R = PF + 1;             // point-wise rings
+  static_assert(W >= 9 + PF && W % R == 0, "ring lengths must fit the window and the unrolled period");
+  constexpr int LR = kWavesPerBlock * kWave + 2 * kRadius;
+  constexpr int CB = 2 * kRadius;  // column bias of the lane offsets
+  // the workgroup's rows of A's input u[n] (with the halos) and of A's result
+  // u[n+1] (for B); rows alternate between two buffer sets
+  __shared__ float xrow[2][2][LR];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  int slot, tile;
+  if (!map_tile(a.d, a.S, a.xcd_map, wv, slot, tile)) return;
+  if (*a.err) return;
+  const SlotInfo si = a.slots[slot];
+  if (si.shot < 0) return;
+  const ShotDesc sd = a.shots[si.shot];
+  const int q = step_of(a);
+  const int n = 2 * q;  // step A: n -> n+1
+  if (n >= sd.nt - 1) return;
+  const bool hasB = n + 1 < sd.nt - 1;
+
+  const Dims& d = a.d;
+  const int xt = tile % d.XT, zt = tile / d.XT;  // xt % 4 == wv
+  const int xs0 = tile2_x0(d.off, xt);
+  Col col = make_col(d, xs0, lane);
+  const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
+  const bool hl_lane = (wv == 0 && lane < 4) || (wv == kWavesPerBlock - 1 && lane >= 4 && lane < 8);
+  col.hsafe = hl_lane ? col.hcol : col.xs;
+  const int cidx = kRadius + kWave * wv + lane;
+  const int hidx = hl_lane ? (lane < 4 ? lane : kWavesPerBlock * kWave + lane) : cidx;
+  const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);  // B's (owned) rows
+  const int za0 = z0 - kRadius, za1 = z1 + kRadius;    // A's rows
+  const int mz_lo = d.N, mz_hi = d.N + d.nz;
+  const bool tile_int = xs0 >= d.mx0 && xs0 + kWave <= d.mx0 + d.nx;
+
+  // level sets: launch q reads set q & 1 and writes the other
+  const int si_ = 3 * (q & 1), so_ = 3 - si_;
+  const int uIn = si_ + (n & 1), dIn = si_ + 2;
+  const int uO1 = so_ + ((n + 1) & 1), uO0 = so_ + (n & 1), dO = so_ + 2;  // u[n+1]; u[n+2] (or u[n]); d
+  float* ubase = a.u + (int64_t)si.cs * a.ustride;
+  const rsrc_t rU = make_rsrc(ubase - d.guard, d.guard + a.ustride);
+  const rsrc_t rW = make_rsrc(a.w - CB, d.field + CB);
+  auto lev = [&](int k) { return (int32_t)((d.guard + (int64_t)k * d.field - CB) * 4); };
+  const int32_t ouIn = lev(uIn), odIn = lev(dIn), ouO1 = lev(uO1), ouO0 = lev(uO0), odO = lev(dO);
+  const int32_t P4 = d.P * 4;
+
+  // strips of u[n+1], u[n+2]; snapshot pairs saved at A or at B
+  float* strip_base = a.strip + (int64_t)si.cs * a.strip_stride;
+  float* stripA = strip_base + (int64_t)(n + 1) * d.ring;
+  float* stripB = strip_base + (int64_t)(n + 2) * d.ring;
+  const int remA = sd.nt - 2 - n, remB = remA - 1;
+  const bool saveA = remA > 0 && (remA % sd.K) == 0;
+  const bool saveB = hasB && remB > 0 && (remB % sd.K) == 0;
+  float* ckpt = a.snap + (int64_t)si.cs * a.snap_stride;
+  float* snA0 = saveA ? ckpt + (int64_t)(remA / sd.K - 1) * 2 * d.model : nullptr;
+  float* snB0 = saveB ? ckpt + (int64_t)(remB / sd.K - 1) * 2 * d.model : nullptr;
+
+  const bool src_tile = sd.src_z >= za0 && sd.src_z < za1 && sd.src_xs >= xs0 && sd.src_xs < xs0 + kWave;
+  const int src_row = src_tile ? sd.src_z : INT_MIN;
+  const float fA = src_tile ? a.wavelet[(int64_t)si.shot * a.wstride + n] : 0.0f;
+  const float fB = (src_tile && hasB) ? a.wavelet[(int64_t)si.shot * a.wstride + n + 1] : 0.0f;
+
+  // bands alternate direction (neighbours read their shared rows together)
+  const int dz = (zt & 1) ? -1 : 1;
+  const int zA0 = dz > 0 ? za0 : za1 - 1;
+  const int nA = za1 - za0;
+  int rpA, rpB, rbeg, rend;
+  {
+    const RmapDir dir = a.rdir[sd.rdir2 + xt];
+    rbeg = dir.begin;
+    rend = dir.begin + dir.count;
+    if (dz > 0) {
+      rpA = rbeg;
+      while (rpA < rend && a.rrows[rpA].z < za0) ++rpA;
+      rpB = rpA;
+      while (rpB < rend && a.rrows[rpB].z < z0) ++rpB;
+    } else {
+      rpA = rend - 1;
+      while (rpA >= rbeg && a.rrows[rpA].z >= za1) --rpA;
+      rpB = rpA;
+      while (rpB >= rbeg && a.rrows[rpB].z >= z1) --rpB;
+    }
+  }
+  auto rz_at = [&](int rp) { return (rp >= rbeg && rp < rend) ? a.rrows[rp].z : INT_MAX; };
+  int rzA = rz_at(rpA), rzB = rz_at(rpB);
+  float* trA = a.traces + (int64_t)(n + 1) * a.ntrace;
+  float* trB = a.traces + (int64_t)(n + 2) * a.ntrace;
+
+  const uint32_t oc = (uint32_t)(col.xs + CB) * 4u;
+  const uint32_t oh = (uint32_t)(col.hsafe + CB) * 4u;
+
+  // rings indexed by sweep position p at slot (p + 4) % W
+  float uc[W];          // A's input u[n]: positions j-4 .. j+5
+  float uo[W], dq[W];   // A's results u[n+1], d[n+1]: positions j-9 .. j
+  float uh[R], pd[R], pw[R];  // A's halo column, d[n], w
+  float wB[R];                // B's w
+  auto load_ptA = [&](int r, float& hu, float& dn, float& w) {
+    hu = bld(rU, oh, ouIn + r * P4);
+    const int rc = clamp_row(d, r);
+    dn = bld(rU, oc, odIn + rc * P4);
+    w = bld(rW, oc, rc * P4);
+  };
+  auto load_ptB = [&](int r, float& w) { w = bld(rW, oc, clamp_row(d, r) * P4); };
+#pragma unroll
+  for (int j = 0; j < 8 + PF; ++j) uc[j] = bld(rU, oc, ouIn + (zA0 + dz * (j - kRadius)) * P4);
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    load_ptA(zA0 + dz * j, uh[j], pd[j], pw[j]);
+    load_ptB(zA0 - dz * (kRadius - j), wB[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < W; ++j) uo[j] = dq[j] = 0.0f;
+
+  for (int jb = 0; jb < nA; jb += W) {
+    static_for<W>([&](auto rc) __attribute__((always_inline)) {
+      constexpr int r = decltype(rc)::value;
+      const int j = jb + r;
+      if (j >= nA) return;
+      const int z = zA0 + dz * j;  // A's row; B's row is 4 rows behind
+      uc[(r + 8 + PF) % W] = bld(rU, oc, ouIn + (z + dz * (kRadius + PF)) * P4);
+      {
+        const int qn = (r + PF) % R;
+        load_ptA(z + dz * PF, uh[qn], pd[qn], pw[qn]);
+        load_ptB(z - dz * (kRadius - PF), wB[qn]);
+      }
+      const int sA = (r + 4) % W, sB = r % W, qa = r % R;
+      float(*xr)[LR] = xrow[r & 1];
+      xr[0][hidx] = uh[qa];
+      xr[0][cidx] = uc[sA];
+      xr[1][cidx] = uo[sB];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      // ---- step A at row z
+      {
+        float lap = laplace<W>(uc, r + 4, xr[0] + kWave * wv, lane);
+        const float c = uc[sA], dn = pd[qa], w = pw[qa];
+        float out = 0.0f, dnew = 0.0f;
+        const bool own_row = z >= z0 && z < z1;
+        if (tile_int && z >= mz_lo && z < mz_hi && z != rzA && z != src_row && !saveA) {
+          dnew = fmaf(w, lap, dn);
+          out = c + dnew;
+        } else if (z >= 0 && z < d.Z) {
+          if (z == src_row && col.xs == sd.src_xs) lap += fA;
+          const Row row = make_row(d, z);
+          if (col.xin) {
+            const int dd = max(row.dz, col.dxs);
+            if (dd == 0) {
+              dnew = fmaf(w, lap, dn);
+            } else {
+              const double gm = a.sp_a * (double)(dd * dd);
+              dnew = (float)(((1.0 - gm) * (double)dn + (double)w * (double)lap) / (1.0 + gm));
+            }
+            out = c + dnew;
+            if (own_row && own_col) {
+              const int ri = strip_index(row, col);
+              if (ri >= 0) stripA[ri] = out;
+              if (saveA && row.model && col.mcol) {
+                const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
+                snA0[mi] = out;
+                snA0[d.model + mi] = c;
+              }
+            }
+          }
+          if (z == rzA) {
+            const int tr = a.rmaps[a.rrows[rpA].map + lane];
+            if (tr >= 0 && own_col) trA[tr] = out;
+            rpA += dz;
+            rzA = rz_at(rpA);
+          }
+        }
+        if (own_row && own_col) {
+          bst(rU, oc, ouO1 + z * P4, out);
+          if (!hasB) {
+            bst(rU, oc, ouO0 + z * P4, c);
+            bst(rU, oc, odO + z * P4, dnew);
+          }
+        }
+        uo[sA] = out;
+        dq[sA] = dnew;
+      }
+      // ---- step B at row z - 4 dz, from sweep position 8 on
+      const int zbB = z - dz * kRadius;
+      if (hasB && j >= 2 * kRadius) {
+        float lap = laplace<W>(uo, r, xr[1] + kWave * wv, lane);
+        const float c = uo[sB], dn = dq[sB], w = wB[r % R];
+        float out, dnew;
+        if (tile_int && zbB >= mz_lo && zbB < mz_hi && zbB != rzB && zbB != src_row && !saveB) {
+          dnew = fmaf(w, lap, dn);
+          out = c + dnew;
+        } else {
+          if (zbB == src_row && col.xs == sd.src_xs) lap += fB;
+          const Row row = make_row(d, zbB);
+          const int dd = max(row.dz, col.dxs);
+          if (dd == 0) {
+            dnew = fmaf(w, lap, dn);
+          } else {
+            const double gm = a.sp_a * (double)(dd * dd);
+            dnew = (float)(((1.0 - gm) * (double)dn + (double)w * (double)lap) / (1.0 + gm));
+          }
+          out = c + dnew;
+          if (own_col) {
+            const int ri = strip_index(row, col);
+            if (ri >= 0) stripB[ri] = out;
+            if (saveB && row.model && col.mcol) {
+              const int64_t mi = (int64_t)row.mz * d.nx + col.mx;
+              snB0[mi] = out;
+              snB0[d.model + mi] = c;
+            }
+          }
+          if (zbB == rzB) {
+            const int tr = a.rmaps[a.rrows[rpB].map + lane];
+            if (tr >= 0 && own_col) trB[tr] = out;
+            rpB += dz;
+            rzB = rz_at(rpB);
+          }
+        }
+        if (own_col) {
+          bst(rU, oc, ouO0 + zbB * P4, out);
+          bst(rU, oc, odO + zbB * P4, dnew);
+        }
+      }
+    });
+  }
+}
+
+// -------------------------------------------------------------------------
 // offset-extended imaging condition over a window of reverse steps:
 //   I(x, h) += sum_slots sum_m lam[m](x - h) D[m](x + h),  |h| <= hmax <= HM
 // One wavefront owns 64 model columns of one model row and keeps the 2HM+1
@@ -1428,6 +1670,34 @@ hipError_t launch_reverse(const StepArgs& a, int prefetch, int flags, hipStream_
     case 14: reverse_fs<3, false, true>(a, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward2(const StepArgs& a, int prefetch, hipStream_t s) {
+  const dim3 grid(step_blocks(a.d, a.S)), block(256);
+  if (prefetch == 3) hipLaunchKernelGGL(k_forward2<3>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_forward2<1>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+// one block row per slot: a shot of nt samples ran nt/2 two-step launches
+// (rounded down: ceil((nt-1)/2)); with an odd count its state is in set 1
+__global__ void k_forward2_finish(float* u, int64_t ustride, int64_t set_floats, const SlotInfo* slots,
+                                  const ShotDesc* shots) {
+  const SlotInfo si = slots[blockIdx.y];
+  if (si.shot < 0) return;
+  if (((shots[si.shot].nt / 2) & 1) == 0) return;
+  float* base = u + (int64_t)si.cs * ustride;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < set_floats;
+       k += (int64_t)gridDim.x * blockDim.x)
+    base[k] = base[set_floats + k];
+}
+
+hipError_t launch_forward2_finish(float* u, int64_t ustride, int64_t set_floats, const SlotInfo* slots,
+                                  const ShotDesc* shots, int S, hipStream_t s) {
+  if (S <= 0 || set_floats <= 0) return hipSuccess;
+  const unsigned bx = (unsigned)std::min<int64_t>((set_floats + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_forward2_finish, dim3(bx, S), dim3(256), 0, s, u, ustride, set_floats, slots, shots);
   return hipGetLastError();
 }
 

@@ -149,6 +149,7 @@ struct Plan {
   int ext_groups = 1;          // partial images (slot groups) of the extended image
   int born = 0;                // Born perturbation wavefield buffers present
   int rev_steps = 1;           // time steps per launch of the plain reverse sweep (1 or 2)
+  int fwd_steps = 1;           // time steps per launch of the gradient's forward sweep (1 or 2)
   int ulevels = kULevels, llevels = kLamLevels;
   int XT2 = 0;                 // tiles of the two-step reverse sweep along x
   double sp_a = 0.0;
@@ -184,7 +185,7 @@ struct Plan {
 // and the reverse sweep's (Sr divides S; 0 = same as the forward's), and the
 // reverse sweep's time steps per launch (1 or 2).
 struct ExecChoice {
-  int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr, rsteps;
+  int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr, rsteps, fsteps;
 };
 
 std::mutex g_mutex;
@@ -288,7 +289,12 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   const bool rev2 = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
                      what == FWI_WS_GNHVP) && !plain && !g->free_surface && ex.rsteps == 2;
   p->rev_steps = rev2 ? 2 : 1;
-  p->ulevels = rev2 ? kULevels2 : kULevels;
+  // two forward steps per launch: the gradient's forward sweep (recording and
+  // checkpoints), not with a free surface; two sets of (u, u, d) levels
+  const bool fwd2 = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE) && !plain &&
+                    !g->free_surface && ex.fsteps == 2;
+  p->fwd_steps = fwd2 ? 2 : 1;
+  p->ulevels = fwd2 ? 2 * kULevels : (rev2 ? kULevels2 : kULevels);
   p->llevels = rev2 ? kLamLevels2 : kLamLevels;
   p->XT2 = kWavesPerBlock * ((d.X + kBlk2 - 1) / kBlk2);
   const double eta_max = 3.0 * g->v_ref * std::log(1e3) / (2.0 * d.N * g->dx);
@@ -348,7 +354,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   // [tile2_x0(t), +64), and the workgroups' column ranges overlap by 8, so a
   // receiver can sit in two tiles
   p->rdir2.assign((size_t)std::max(ns, 1) * std::max(p->XT2, 1), RmapDir{0, 0});
-  if (rev2) {
+  if (rev2 || fwd2) {
     for (int s = 0; s < ns; ++s) {
       std::map<std::pair<int, int>, std::vector<int>> rows;  // (tile, z) -> traces
       for (int r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r) {
@@ -551,8 +557,11 @@ hipError_t get_capture_stream(hipStream_t* out) {
 int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, const float* wavelet,
               int64_t wstride, hipStream_t stream) {
   if (nsteps <= 0) return FWI_OK;
-  // the plain reverse sweep of a two-step plan: launches of two steps each
-  const bool two = phase == kPhaseRev && flags == 0 && p.rev_steps == 2;
+  // the plain reverse sweep of a two-step plan, or the gradient's forward
+  // sweep of one: launches of two steps each
+  const bool two_rev = phase == kPhaseRev && flags == 0 && p.rev_steps == 2;
+  const bool two_fwd = phase == kPhaseFwd && flags == (kFwdRecord | kFwdCkpt) && p.fwd_steps == 2;
+  const bool two = two_rev || two_fwd;
   if (two) nsteps = (nsteps + 1) / 2;
   StepArgs a = step_args(p, ws, batch, phase, wavelet, wstride, two);
   // reverse sweeps with kRevExt keep lam and D of the last ext_T steps and
@@ -561,7 +570,8 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   if (ext && p.ext_h < 0) return fail(FWI_ERR_STATE, "extended image without its buffers");
   ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
-    if (two) return launch_reverse2(args, p.pf_rev, s);
+    if (two_rev) return launch_reverse2(args, p.pf_rev, s);
+    if (two_fwd) return launch_forward2(args, p.pf_fwd == 1 ? 1 : 3, s);
     return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
                               : launch_reverse(args, p.pf_rev, flags, s);
   };
@@ -683,7 +693,11 @@ int forward_batch(Plan& p, void* ws, int b, int flags, const float* wavelet, int
   if (flags & kFwdBorn)
     HIP_TRY(launch_fill_slots(at<float>(ws, p.L.bu), kULevels * p.d.field, kULevels * p.d.field + p.d.guard, slots,
                               p.S, 1, s));
-  return run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s);
+  if (int rc = run_steps(p, ws, b, kPhaseFwd, flags, p.batch_nt[b] - 1, wavelet, wstride, s)) return rc;
+  if (flags == (kFwdRecord | kFwdCkpt) && p.fwd_steps == 2)
+    HIP_TRY(launch_forward2_finish(at<float>(ws, p.L.u) + p.d.guard, p.ulevels * p.d.field, kULevels * p.d.field,
+                                   slots, at<ShotDesc>(ws, p.L.shots), p.S, s));
+  return FWI_OK;
 }
 
 int misfit_batch(Plan& p, void* ws, int b, const float* d_obs, int misfit, hipStream_t s) {
@@ -799,6 +813,13 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   else RSs = {1, 2};
   const bool grad = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE ||
                      what == FWI_WS_GNHVP);
+  // forward time steps per launch: two for the gradient's forward sweep
+  // (not the Born one), tried first so that near-ties keep the fewer bytes
+  std::vector<int> FSs;
+  if (ex && ex->forward_steps > 0) FSs = {ex->forward_steps};
+  else if (g->free_surface || !(what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE))
+    FSs = {1};
+  else FSs = {2, 1};
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
   const int nsteps = 32;
   // FWI_TUNE_LOG set: each candidate's best time goes to stderr
@@ -809,7 +830,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
                     time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s));
   };
   struct Cand {
-    int S, TZ, pf, rs;
+    int S, TZ, pf, rs, fs;
     double per_shot;  // ms per shot and step
   };
   std::vector<Cand> F, Rv;
@@ -824,7 +845,8 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
                       std::find(SRs.begin(), SRs.end(), S) != SRs.end();
       if (!tf && !tr) continue;
       const int rs_max = *std::max_element(RSs.begin(), RSs.end());
-      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max};
+      const int fs_max = *std::max_element(FSs.begin(), FSs.end());
+      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max, fs_max};
       auto p = build_plan(g, geo, c, 0, what, 0);
       if (p->L.total > ws_bytes) continue;
       if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
@@ -834,15 +856,20 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       // resolve to the shorter one from run to run
       if (tf) {
         double fb = 1e30;
-        int fpf = PFs[0];
-        for (int pf : PFs) {
-          p->pf_fwd = pf;
-          const double ms = timed(*p, fwd_flags, kPhaseFwd);
-          if (ms < fb * 0.98) { fb = ms; fpf = pf; }
+        int fpf = PFs[0], ffs = FSs[0];
+        for (int fs : FSs) {
+          for (int pf : PFs) {
+            if (fs == 2 && pf == 7) continue;  // the two-step sweep prefetches 1 or 3 rows
+            p->fwd_steps = fs;
+            p->pf_fwd = pf;
+            const double ms = timed(*p, fwd_flags, kPhaseFwd);
+            if (ms < fb * 0.98) { fb = ms; fpf = pf; ffs = fs; }
+          }
         }
-        F.push_back(Cand{S, TZ, fpf, 1, fb / shots});
-        if (tune_log) fprintf(stderr, "[fwi tune] forward S %d TZ %d PF %d: %.3f us per shot-step\n", S, TZ, fpf,
-                              1e3 * fb / shots / nsteps);
+        F.push_back(Cand{S, TZ, fpf, 1, ffs, fb / shots});
+        if (tune_log)
+          fprintf(stderr, "[fwi tune] forward S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, fpf, ffs,
+                  1e3 * fb / shots / nsteps);
       }
       if (tr) {
         double rb = 1e30;
@@ -855,7 +882,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
             if (ms < rb * 0.98) { rb = ms; rpf = pf; rrs = rs; }
           }
         }
-        Rv.push_back(Cand{S, TZ, rpf, rrs, rb / shots});
+        Rv.push_back(Cand{S, TZ, rpf, rrs, 1, rb / shots});
         if (tune_log)
           fprintf(stderr, "[fwi tune] reverse S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, rpf, rrs,
                   1e3 * rb / shots / nsteps);
@@ -879,7 +906,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     if (!grad) {
       if (f.per_shot < best_t * 0.98) {
         best_t = f.per_shot;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ, 1};
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ, 1, 1};
       }
       continue;
     }
@@ -888,7 +915,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       const double t = f.per_shot + r.per_shot;
       if (t < best_t * 0.98) {
         best_t = t;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ, r.rs};
+        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ, r.rs, f.fs};
       }
     }
   }
@@ -913,6 +940,7 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.Sr = (ex && ex->shots_in_flight_reverse > 0) ? ex->shots_in_flight_reverse : 0;
   c.TZr = (ex && ex->tile_rows_reverse > 0) ? ex->tile_rows_reverse : 0;
   c.rsteps = (ex && ex->reverse_steps > 0) ? ex->reverse_steps : 1;
+  c.fsteps = (ex && ex->forward_steps > 0) ? ex->forward_steps : 1;
   return c;
 }
 
@@ -929,7 +957,8 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
                              (uint64_t)(ex ? ex->prefetch_reverse : 0),
                              (uint64_t)(ex ? ex->shots_in_flight_reverse : 0),
                              (uint64_t)(ex ? ex->tile_rows_reverse : 0),
-                             (uint64_t)(ex ? ex->reverse_steps : 0)};
+                             (uint64_t)(ex ? ex->reverse_steps : 0),
+                             (uint64_t)(ex ? ex->forward_steps : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -975,9 +1004,9 @@ bool cache_lookup(const std::vector<uint64_t>& k, ExecChoice& c) {
     if (!colon) continue;
     if (std::string(line, colon - line) != want) continue;
     ExecChoice t{};
-    if (sscanf(colon + 1, "%d %d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
-               &t.TZr, &t.rsteps) == 8 &&
-        (t.rsteps == 1 || t.rsteps == 2) &&
+    if (sscanf(colon + 1, "%d %d %d %d %d %d %d %d %d", &t.S, &t.TZ, &t.graph_steps, &t.pf_fwd, &t.pf_rev, &t.Sr,
+               &t.TZr, &t.rsteps, &t.fsteps) == 9 &&
+        (t.rsteps == 1 || t.rsteps == 2) && (t.fsteps == 1 || t.fsteps == 2) &&
         t.Sr > 0 && t.TZr >= 8 && t.TZr <= 4096 &&
         t.S > 0 && t.TZ >= 8 && t.TZ <= 4096 && (t.graph_steps == -1 || (t.graph_steps > 0 && t.graph_steps <= 1024)) &&
         (t.pf_fwd == 1 || t.pf_fwd == 3 || t.pf_fwd == 7) &&
@@ -995,8 +1024,8 @@ void cache_store(const std::vector<uint64_t>& k, const ExecChoice& c) {
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s: %d %d %d %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd, c.pf_rev,
-          c.Sr, c.TZr, c.rsteps);
+  fprintf(f, "%s: %d %d %d %d %d %d %d %d %d\n", key_text(k).c_str(), c.S, c.TZ, c.graph_steps, c.pf_fwd,
+          c.pf_rev, c.Sr, c.TZr, c.rsteps, c.fsteps);
   fclose(f);
 }
 
@@ -1015,6 +1044,7 @@ int check_exec(const fwi_exec* ex) {
   if (ex && ex->prefetch_reverse != 0 && ex->prefetch_reverse != 1 && ex->prefetch_reverse != 3)
     return fail(FWI_ERR_ARG, "prefetch_reverse must be 0, 1 or 3");
   if (ex && (ex->reverse_steps < 0 || ex->reverse_steps > 2)) return fail(FWI_ERR_ARG, "reverse_steps must be 0, 1 or 2");
+  if (ex && (ex->forward_steps < 0 || ex->forward_steps > 2)) return fail(FWI_ERR_ARG, "forward_steps must be 0, 1 or 2");
   return FWI_OK;
 }
 
@@ -1032,7 +1062,8 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     if (!(ex->shots_in_flight > 0)) c.S = std::min(std::max(geo->nshot, 1), 64);
     if (!(ex->tile_rows > 0)) c.TZ = 32;
     c.Sr = 0;  // reverse buffers sized for the forward's maximum
-    if (!(ex->reverse_steps > 0)) c.rsteps = 2;  // and for the two-step sweep's levels
+    if (!(ex->reverse_steps > 0)) c.rsteps = 2;  // and for the two-step sweeps' levels
+    if (!(ex->forward_steps > 0)) c.fsteps = 2;
   }
   if (tune) {
     const auto tk = tune_key(g, geo, ex, what);
@@ -1064,6 +1095,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.Sr);
   h.pod(c.TZr);
   h.pod(c.rsteps);
+  h.pod(c.fsteps);
   h.pod(ext_h);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
@@ -1151,6 +1183,10 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
         resolve_sr(chosen->shots_in_flight, c.Sr, plain, what == FWI_WS_AUTOGRAD, geom->nshot);
     chosen->tile_rows_reverse = c.TZr > 0 ? c.TZr : c.TZ;
     chosen->reverse_steps = (plain || grid->free_surface) ? 1 : c.rsteps;
+    chosen->forward_steps = (plain || grid->free_surface || what == FWI_WS_FORWARD || what == FWI_WS_HESSIAN ||
+                             what == FWI_WS_BORN || what == FWI_WS_GNHVP)
+                                ? 1
+                                : c.fsteps;
   }
   return FWI_OK;
 }

@@ -179,6 +179,17 @@ def test_reverse_launch_settings(lib):
     assert q["shots_in_flight_reverse"] == 3
     q = B.fwi_exec_query(w.grid, w.geom, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=99), B.WS_AUTOGRAD)
     assert q["shots_in_flight_reverse"] == 8
+    # two forward steps per launch: the gradient's forward sweep only
+    for what, want in ((B.WS_GRADIENT, 2), (B.WS_AUTOGRAD, 2), (B.WS_EXTIMAGE, 2), (B.WS_FORWARD, 1),
+                       (B.WS_BORN, 1), (B.WS_GNHVP, 1), (B.WS_HESSIAN, 1)):
+        assert B.fwi_exec_query(w.grid, w.geom, B.make_exec(forward_steps=2), what)["forward_steps"] == want, what
+    assert B.fwi_exec_query(w.grid, w.geom, B.make_exec(forward_steps=2, mode=B.EXEC_PLAIN),
+                            B.WS_GRADIENT)["forward_steps"] == 1
+    with pytest.raises(B.FwiError):
+        B.fwi_exec_query(w.grid, w.geom, B.make_exec(forward_steps=3), B.WS_GRADIENT)
+    a = B.fwi_workspace_bytes(w.grid, w.geom, B.make_exec(forward_steps=2), B.WS_GRADIENT)
+    b = B.fwi_workspace_bytes(w.grid, w.geom, B.make_exec(forward_steps=1), B.WS_GRADIENT)
+    assert a > b                          # two sets of wavefield levels
     g, geo = _tiny()
     with pytest.raises(B.FwiError) as e:
         B.fwi_exec_query(g, geo, B.make_exec(tile_rows_reverse=4), B.WS_GRADIENT)

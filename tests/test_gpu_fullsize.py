@@ -66,12 +66,13 @@ def test_layered_1024x384_short_record(S, TZ):
           np.repeat(both, rs, axis=0), mult=4.0)
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "two_step", "two_step_pf3"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "two_step", "two_step_pf3", "fwd_two_step"])
 def test_layered_1024x384_full_record(mode):
     z, w, grid, geom, wav, d_obs = golden("layered_1024x384_nt4000")
     ex = {"plain": B.make_exec(mode=B.EXEC_PLAIN), "batched": B.make_exec(autotune=1),
           "two_step": B.make_exec(reverse_steps=2, tile_rows_reverse=16),
-          "two_step_pf3": B.make_exec(reverse_steps=2, tile_rows_reverse=32, prefetch_reverse=3)}[mode]
+          "two_step_pf3": B.make_exec(reverse_steps=2, tile_rows_reverse=32, prefetch_reverse=3),
+          "fwd_two_step": B.make_exec(forward_steps=2, reverse_steps=2, tile_rows=32, tile_rows_reverse=32)}[mode]
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
     check(f"layered nt4000 {mode}", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr)
@@ -85,7 +86,7 @@ def test_layered_2048x768_full_record_offset_diag():
     check("layered 2048x768 nt8000", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr, D=D.cpu().numpy())
 
 
-@pytest.mark.parametrize("steps", [0, 2])
+@pytest.mark.parametrize("steps", [0, 2, 22])
 def test_ragged_1024x384_extremes_batched(steps):
     """The shortest (nt 2013, 264 receivers) and the longest (nt 5988, 798
     receivers) record of the 256-shot ragged workload, each repeated 4 times:
@@ -96,7 +97,8 @@ def test_ragged_1024x384_extremes_batched(steps):
     z, w, grid, geom2, wav, d2 = golden("ragged_1024x384_extremes")
     geom = geom2.subset([0, 1] * 4)
     d_obs = np.concatenate([d2] * 4)
-    ex = B.make_exec(autotune=1, reverse_steps=steps)
+    # 22: two forward and two reverse steps per launch
+    ex = B.make_exec(autotune=1, reverse_steps=steps % 10, forward_steps=steps // 10)
     tr = B.forward(w.v_start, wav, grid, geom, ex).cpu().numpy()
     J, g, H1, _ = B.gradient(w.v_start, wav, grid, geom, d_obs, "int", ex)
     check("ragged extremes x4", z, float(J), g.cpu().numpy(), H1.cpu().numpy(), tr[:geom2.ntrace], mult=4.0)

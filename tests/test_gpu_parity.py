@@ -34,6 +34,11 @@ EXECS = {
     "two_step": B.make_exec(shots_in_flight=3, tile_rows=16, graph_steps=-1, reverse_steps=2),
     "two_step_graph": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=24, tile_rows_reverse=12,
                                   graph_steps=5, reverse_steps=2, prefetch_reverse=3),
+    # two forward steps per launch (with one-step and two-step reverse sweeps)
+    "fwd_two_step": B.make_exec(shots_in_flight=3, tile_rows=16, graph_steps=-1, forward_steps=2),
+    "both_two_step_graph": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=12,
+                                       tile_rows_reverse=24, graph_steps=5, reverse_steps=2, forward_steps=2,
+                                       prefetch=3),
 }
 
 

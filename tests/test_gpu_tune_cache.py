@@ -1,7 +1,7 @@
 """The autotuner's choices persist across processes through FWI_TUNE_CACHE.
 
 A tuned forward call appends one line (key : S TZ graph_steps prefetch
-prefetch_reverse S_rev TZ_rev reverse_steps) to the file.  After fwi_tune_reset (which stands for a
+prefetch_reverse S_rev TZ_rev reverse_steps forward_steps) to the file.  After fwi_tune_reset (which stands for a
 fresh process) the library reads the file back instead of tuning again, and
 its results still match the oracle.
 """
@@ -42,7 +42,7 @@ def test_tuned_choice_round_trips_through_file(tmp_path, monkeypatch):
     first = lines(cache)
     assert len(first) == 1, first
     key, choice = first[0].split(":")
-    S, TZ, G, PF, PR, SR, TZR, RS = (int(t) for t in choice.split())
+    S, TZ, G, PF, PR, SR, TZR, RS, FS = (int(t) for t in choice.split())
     q = B.fwi_exec_query(w.grid, w.geom, ex, B.WS_FORWARD)
     assert q["shots_in_flight"] == min(S, w.geom.nshot)
     assert chosen(q) == (TZ, G, PF, PR)
@@ -52,7 +52,7 @@ def test_tuned_choice_round_trips_through_file(tmp_path, monkeypatch):
     TZ2 = 32 if TZ != 32 else 16
     PF2 = 7 if PF != 7 else 3
     with open(cache, "w") as f:
-        f.write(f"{key}: {S} {TZ2} {G} {PF2} 3 {SR} {TZR} {RS}\n")
+        f.write(f"{key}: {S} {TZ2} {G} {PF2} 3 {SR} {TZR} {RS} {FS}\n")
     B.fwi_tune_reset()
     assert chosen(B.fwi_exec_query(w.grid, w.geom, ex, B.WS_FORWARD)) == (TZ2, G, PF2, 3)
     got2 = B.forward(w.v_true, w.wavelet, w.grid, w.geom, ex).cpu().numpy()
