@@ -962,9 +962,9 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
 // A's results u[n+1], d[n+1] of the last 10 (12) rows in register rings.
 // The u levels hold two sets of (u[k] at k & 1, d) in levels 0-2 and 3-5: a
 // launch reads one set and writes u[n+1], u[n+2], d[n+2] into the other
-// (neighbouring workgroups read the inputs in their overlap).  A shot whose
-// last launch ends after A (an odd number of steps) stores u[n], u[n+1],
-// d[n+1] instead.  Strips, snapshots and traces are written by the step
+// (neighbouring workgroups read the inputs in their overlap); u[n+1] only in
+// a shot's last launch.  A shot whose last launch ends after A (an odd
+// number of steps) stores u[n], u[n+1], d[n+1] instead.  Strips, snapshots and traces are written by the step
 // that produces them, as in the one-step sweep.
 // -------------------------------------------------------------------------
 template <int PF>
@@ -989,6 +989,9 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
   const int n = 2 * q;  // step A: n -> n+1
   if (n >= sd.nt - 1) return;
   const bool hasB = n + 1 < sd.nt - 1;
+  // u[n+1] is stored only by the shot's last launch (the reverse sweep starts
+  // from u[nt-1], u[nt-2]); the next launch reads u[n+2] and d[n+2] only
+  const bool keep1 = n + 2 >= sd.nt - 1;
 
   const Dims& d = a.d;
   const int xt = tile % d.XT, zt = tile / d.XT;  // xt % 4 == wv
@@ -1141,7 +1144,7 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
           }
         }
         if (own_row && own_col) {
-          bst(rU, oc, ouO1 + z * P4, out);
+          if (keep1) bst(rU, oc, ouO1 + z * P4, out);
           if (!hasB) {
             bst(rU, oc, ouO0 + z * P4, c);
             bst(rU, oc, odO + z * P4, dnew);

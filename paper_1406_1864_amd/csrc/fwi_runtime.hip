@@ -845,27 +845,37 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
                       std::find(SRs.begin(), SRs.end(), S) != SRs.end();
       if (!tf && !tr) continue;
       const int rs_max = *std::max_element(RSs.begin(), RSs.end());
-      const int fs_max = *std::max_element(FSs.begin(), FSs.end());
-      ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max, fs_max};
-      auto p = build_plan(g, geo, c, 0, what, 0);
-      if (p->L.total > ws_bytes) continue;
-      if (begin_call(*p, ws, v, s) != FWI_OK) return FWI_ERR_HIP;
-      HIP_TRY(launch_fill(at<char>(ws, p->L.u), p->L.g - p->L.u, s));
       const double shots = std::min(S, std::max(ns, 1));
+      // each candidate runs in a plan of its own layout (the two-step forward
+      // sweep has twice the wavefield levels)
+      auto prepare = [&](int fs) -> std::shared_ptr<Plan> {
+        ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max, fs};
+        auto p = build_plan(g, geo, c, 0, what, 0);
+        if (p->L.total > ws_bytes) return nullptr;
+        if (begin_call(*p, ws, v, s) != FWI_OK) return nullptr;
+        if (launch_fill(at<char>(ws, p->L.u), p->L.g - p->L.u, s) != hipSuccess) return nullptr;
+        return p;
+      };
       // within one (S, TZ) a longer prefetch must win by 2 %, so near-ties
       // resolve to the shorter one from run to run
-      if (tf) {
-        double fb = 1e30;
-        int fpf = PFs[0], ffs = FSs[0];
-        for (int fs : FSs) {
-          for (int pf : PFs) {
-            if (fs == 2 && pf == 7) continue;  // the two-step sweep prefetches 1 or 3 rows
-            p->fwd_steps = fs;
-            p->pf_fwd = pf;
-            const double ms = timed(*p, fwd_flags, kPhaseFwd);
-            if (ms < fb * 0.98) { fb = ms; fpf = pf; ffs = fs; }
-          }
+      double fb = 1e30;
+      int fpf = PFs[0], ffs = FSs[0];
+      std::shared_ptr<Plan> p;
+      for (int fs : FSs) {
+        p = prepare(fs);
+        if (!p) continue;
+        if (!tf) continue;
+        for (int pf : PFs) {
+          if (fs == 2 && pf == 7) continue;  // the two-step sweep prefetches 1 or 3 rows
+          p->pf_fwd = pf;
+          const double ms = timed(*p, fwd_flags, kPhaseFwd);
+          if (ms < fb * 0.98) { fb = ms; fpf = pf; ffs = fs; }
         }
+      }
+      if (!p || p->fwd_steps != 1) {  // the reverse timings run in the one-step forward layout
+        if (!(p = prepare(1))) continue;
+      }
+      if (tf && fb < 1e29) {
         F.push_back(Cand{S, TZ, fpf, 1, ffs, fb / shots});
         if (tune_log)
           fprintf(stderr, "[fwi tune] forward S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, fpf, ffs,
