@@ -25,7 +25,8 @@ def anomaly():
 
 @pytest.mark.parametrize("exec_", [None, B.make_exec(graph_steps=-1), B.make_exec(mode=B.EXEC_PLAIN),
                                    B.make_exec(shots_in_flight=2, shots_in_flight_reverse=1, tile_rows_reverse=12),
-                                   B.make_exec(reverse_steps=2, graph_steps=7)])
+                                   B.make_exec(reverse_steps=2, graph_steps=7),
+                                   B.make_exec(forward_steps=2, reverse_steps=2, graph_steps=6)])
 def test_autograd_matches_oracle(anomaly, exec_):
     w, d_obs, (J, g, H1, E, syn) = anomaly
     pr = FWIProblem(w.grid, w.geom, w.wavelet, d_obs.astype(np.float32), "int", exec_, hmax=4)
@@ -44,7 +45,9 @@ def test_autograd_matches_oracle(anomaly, exec_):
 
 @pytest.mark.parametrize("exec_", [
     B.make_exec(shots_in_flight=1, shots_in_flight_reverse=3, reverse_steps=2, graph_steps=5),
-    B.make_exec(shots_in_flight=2, shots_in_flight_reverse=4, tile_rows_reverse=8, graph_steps=-1)])
+    B.make_exec(shots_in_flight=2, shots_in_flight_reverse=4, tile_rows_reverse=8, graph_steps=-1),
+    # two forward steps per launch as well (odd and even record lengths)
+    B.make_exec(shots_in_flight=2, shots_in_flight_reverse=5, reverse_steps=2, forward_steps=2, graph_steps=3)])
 def test_autograd_ragged_reverse_groups(exec_):
     """The autograd pair keeps every shot's checkpoints, so its reverse sweep
     groups the shots on its own: groups larger than the forward batches, the
