@@ -135,13 +135,13 @@ typedef struct {
                                  tuned, or tile_rows                           */
     int32_t reverse_steps;    /* time steps per launch of the adjoint sweep of
                                  fwi_gradient / fwi_misfit_backward /
-                                 fwi_gn_hvp: 1, or 2 (temporal blocking: a
-                                 workgroup computes the first step on 256
-                                 columns and the second on the 248 inside, one
-                                 read and one write of every field for both);
-                                 0 = tuned, else 1.  Two steps are
-                                 not used with a free surface, in plain mode or
-                                 for the extended image / eq. (3) variants     */
+                                 fwi_gn_hvp / fwi_extended_image: 1, or 2
+                                 (temporal blocking: a workgroup computes the
+                                 first step on 256 columns and the second on
+                                 the 248 inside, one read and one write of
+                                 every field for both); 0 = tuned, else 1.
+                                 Two steps are not used with a free surface,
+                                 in plain mode or for the eq. (3) variant      */
     int32_t forward_steps;    /* time steps per launch of the forward sweep
                                  of fwi_gradient / fwi_misfit_forward /
                                  fwi_extended_image: 1, or 2 (the same

@@ -128,8 +128,9 @@ struct ExtArgs {
   float* I;             // [groups][2 hmax + 1][model]: one partial sum per slot group
   int32_t hmax;
   int32_t groups;       // slots are split into this many groups (parallelism)
-  const int32_t* step_ctr;
-  int32_t step0, count;
+  const int32_t* step_ctr;  // launches done (graph replays), or null
+  int32_t step_mul;         // reverse steps per launch: the window starts at step_mul * *step_ctr + step0
+  int32_t step0, count;     // in reverse steps
   const int32_t* err;
 };
 
@@ -183,7 +184,7 @@ hipError_t launch_ext_image(const ExtArgs& a, hipStream_t s);
 // two reverse steps per launch (StepArgs::d.XT = two-step tiles, receiver
 // maps of that tiling, step = launch index); no extended image, eq. (3) or
 // free surface
-hipError_t launch_reverse2(const StepArgs& a, int prefetch, hipStream_t s);
+hipError_t launch_reverse2(const StepArgs& a, int prefetch, int flags, hipStream_t s);
 hipError_t launch_forward2(const StepArgs& a, int prefetch, hipStream_t s);
 // after a two-step forward sweep: shots whose final state sits in the second
 // set of u levels (an odd number of launches) get it copied to the first

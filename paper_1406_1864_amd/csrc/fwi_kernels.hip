@@ -645,7 +645,7 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float
 
 // (at least 4 wavefronts per SIMD: the compiler keeps the deeper prefetch
 // within 128 VGPRs)
-template <int PF>
+template <int PF, bool EXT>
 __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
   // PF: rows of loads in flight ahead of A (1 or 3)
   constexpr int W = PF == 1 ? 10 : 12;  // register rings: the unrolled period
@@ -707,6 +707,12 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
   float* lbase = a.lam + (int64_t)slot * a.lstride;
   float* G = a.g + (int64_t)slot * d.model;
   float* E = a.E + (int64_t)slot * d.model;
+  // extended imaging: lam and D of both steps (reverse steps 2q, 2q+1) into
+  // the slot's ring of ext_T steps
+  float* xlA = EXT ? a.ext_lam + ((int64_t)slot * a.ext_T + (2 * q) % a.ext_T) * d.model : nullptr;
+  float* xdA = EXT ? a.ext_D + ((int64_t)slot * a.ext_T + (2 * q) % a.ext_T) * d.model : nullptr;
+  float* xlB = EXT ? a.ext_lam + ((int64_t)slot * a.ext_T + (2 * q + 1) % a.ext_T) * d.model : nullptr;
+  float* xdB = EXT ? a.ext_D + ((int64_t)slot * a.ext_T + (2 * q + 1) % a.ext_T) * d.model : nullptr;
   const float* strip_base = a.strip + (int64_t)si.cs * a.strip_stride;
   // resources: this slot's u levels and lam levels with the guard rows in
   // front, w, g and E of the slot (E at a fixed offset after g), the strips
@@ -875,6 +881,11 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
         if (z >= z0 && z < z1 && own_col) {
           bst(rU, oc, ouO0 + z * P4, uo_);
           bst(rL, oc, olO0 + z * P4, lo_);
+          if (EXT && z >= mz_lo && z < mz_hi && col.mcol) {
+            const int64_t mi = (int64_t)(z - d.N) * d.nx + col.mx;
+            xlA[mi] = lo_;
+            xdA[mi] = d_;
+          }
         }
         uo[sA] = uo_;
         lo[sA] = lo_;
@@ -887,11 +898,12 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
         float lapLB = laplace<W>(lo, r, xr[3] + kWave * wv, lane);
         float lapUB = laplace<W>(uo, r, xr[2] + kWave * wv, lane);
         const float w = wB[qb], cu = uo[sB], cl = lo[sB], pu = uc[sB], pl1 = lc[sB], da = dA[sB];
-        float l1 = 0.0f, u1 = 0.0f, gn = 0.0f, en = 0.0f;
+        float l1 = 0.0f, u1 = 0.0f, gn = 0.0f, en = 0.0f, dB = 0.0f;
         bool st_l = own_col, st_u = own_col, st_g = own_col;
         if (tile_int && zbB >= mz_lo && zbB < mz_hi && zbB != rzB && zbB != src_row && hasB) {
           l1 = fmaf(w, lapLB, 2.0f * cl - pl1);
           const float D = w * lapUB;
+          dB = D;
           u1 = fmaf(w, lapUB, 2.0f * cu - pu);
           gn = fmaf(l1, D, fmaf(cl, da, gB[qb]));
           en = fmaf(D, D, fmaf(da, da, first ? 0.0f : eB[qb]));
@@ -912,6 +924,7 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
             const float ae = fmaf(da, da, first ? 0.0f : eB[qb]);
             l1 = fmaf(w, lapLB, 2.0f * cl - pl1);
             const float D = w * lapUB;
+            dB = D;
             u1 = fmaf(w, lapUB, 2.0f * cu - pu);
             gn = hasB ? fmaf(l1, D, ag) : ag;
             en = hasB ? fmaf(D, D, ae) : ae;
@@ -928,6 +941,11 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
           const int32_t mo = mrow4(zbB);
           bst(rG, om, mo, gn);
           bst(rG, om, mo + oE, en);
+          if (EXT && hasB) {  // (st_g: a model cell of this wavefront)
+            const int64_t mi = (int64_t)(zbB - d.N) * d.nx + col.mx;
+            xlB[mi] = l1;
+            xdB[mi] = dB;
+          }
         }
       }
     });
@@ -1223,7 +1241,7 @@ __global__ __launch_bounds__(256) void k_ext_image(ExtArgs a) {
   float* shL = shL_all[wv];
   float* shD = shD_all[wv];
   const int H = a.hmax;
-  const int j0 = (a.step_ctr ? *a.step_ctr : 0) + a.step0;
+  const int j0 = (a.step_ctr ? a.step_mul * *a.step_ctr : 0) + a.step0;
   float acc[2 * HM + 1];
 #pragma unroll
   for (int h = 0; h < 2 * HM + 1; ++h) acc[h] = 0.0f;
@@ -1283,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_ext_image4(ExtArgs a) {
   const int spg = (a.S + a.groups - 1) / a.groups;
   const int s_lo = grp * spg, s_hi = min(a.S, s_lo + spg);
   const int H = a.hmax;
-  const int j0 = (a.step_ctr ? *a.step_ctr : 0) + a.step0;
+  const int j0 = (a.step_ctr ? a.step_mul * *a.step_ctr : 0) + a.step0;
   const int n_it = max(s_hi - s_lo, 0) * a.count;
   float* shL = shL_all[wv];
   float* shD = shD_all[wv];
@@ -1704,10 +1722,16 @@ hipError_t launch_forward2_finish(float* u, int64_t ustride, int64_t set_floats,
   return hipGetLastError();
 }
 
-hipError_t launch_reverse2(const StepArgs& a, int prefetch, hipStream_t s) {
+hipError_t launch_reverse2(const StepArgs& a, int prefetch, int flags, hipStream_t s) {
   const dim3 grid(step_blocks(a.d, a.S)), block(256);
-  if (prefetch == 3) hipLaunchKernelGGL(k_reverse2<3>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(k_reverse2<1>, grid, block, 0, s, a);
+  const bool ext = (flags & kRevExt) != 0;
+  if (prefetch == 3) {
+    if (ext) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reverse2<3, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reverse2<3, false>), grid, block, 0, s, a);
+  } else {
+    if (ext) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reverse2<1, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reverse2<1, false>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -434,7 +434,9 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   p->born = (what == FWI_WS_BORN || what == FWI_WS_GNHVP) ? 1 : 0;
   const bool ext = (what == FWI_WS_EXTIMAGE && ext_h >= 0);
   p->ext_h = ext ? ext_h : -1;
-  p->ext_T = ext ? (p->graph_steps > 0 ? p->graph_steps : 32) : 0;
+  // the ring holds the reverse steps of one graph chunk (two per launch for
+  // the two-step sweep)
+  p->ext_T = ext ? (p->graph_steps > 0 ? p->graph_steps : 32) * p->rev_steps : 0;
   Layout& L = p->L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -536,6 +538,7 @@ ExtArgs ext_args(const Plan& p, void* ws, int rbatch) {
   e.hmax = p.ext_h;
   e.groups = p.ext_groups;
   e.step_ctr = nullptr;
+  e.step_mul = 1;
   e.step0 = 0;
   e.count = 0;
   e.err = &at<Header>(ws, p.L.hdr)->err;
@@ -559,9 +562,10 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   if (nsteps <= 0) return FWI_OK;
   // the plain reverse sweep of a two-step plan, or the gradient's forward
   // sweep of one: launches of two steps each
-  const bool two_rev = phase == kPhaseRev && flags == 0 && p.rev_steps == 2;
+  const bool two_rev = phase == kPhaseRev && (flags & ~kRevExt) == 0 && p.rev_steps == 2;
   const bool two_fwd = phase == kPhaseFwd && flags == (kFwdRecord | kFwdCkpt) && p.fwd_steps == 2;
   const bool two = two_rev || two_fwd;
+  const int total_steps = nsteps;  // time steps (the extended image counts these)
   if (two) nsteps = (nsteps + 1) / 2;
   StepArgs a = step_args(p, ws, batch, phase, wavelet, wstride, two);
   // reverse sweeps with kRevExt keep lam and D of the last ext_T steps and
@@ -569,26 +573,34 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   const bool ext = phase == kPhaseRev && (flags & kRevExt);
   if (ext && p.ext_h < 0) return fail(FWI_ERR_STATE, "extended image without its buffers");
   ExtArgs e = ext ? ext_args(p, ws, batch) : ExtArgs{};
+  const int spl = two ? 2 : 1;  // time steps per launch
+  e.step_mul = spl;
   auto launch = [&](const StepArgs& args, hipStream_t s) -> hipError_t {
-    if (two_rev) return launch_reverse2(args, p.pf_rev, s);
+    if (two_rev) return launch_reverse2(args, p.pf_rev, flags, s);
     if (two_fwd) return launch_forward2(args, p.pf_fwd == 1 ? 1 : 3, s);
     return phase == kPhaseFwd ? launch_forward(args, flags, p.pf_fwd, s)
                               : launch_reverse(args, p.pf_rev, flags, s);
   };
   const int T = p.graph_steps;
+  // fold the ring after the launch that completes a window of ext_T steps,
+  // or the sweep; `done` time steps so far
+  auto fold_direct = [&](int k) -> hipError_t {
+    const int done = std::min(spl * (k + 1), total_steps);
+    if (!(done % p.ext_T == 0 || k == nsteps - 1)) return hipSuccess;
+    e.step_ctr = nullptr;
+    e.step0 = (done - 1) - (done - 1) % p.ext_T;
+    e.count = done - e.step0;
+    return launch_ext_image(e, stream);
+  };
   if (T <= 0) {
     for (int k = 0; k < nsteps; ++k) {
       a.step = k;
       HIP_TRY(launch(a, stream));
-      if (ext && ((k + 1) % p.ext_T == 0 || k == nsteps - 1)) {
-        e.step0 = k - k % p.ext_T;
-        e.count = k % p.ext_T + 1;
-        HIP_TRY(launch_ext_image(e, stream));
-      }
+      if (ext) HIP_TRY(fold_direct(k));
     }
     return FWI_OK;
   }
-  if (ext && p.ext_T != T) return fail(FWI_ERR_STATE, "extended-image ring differs from the graph chunk");
+  if (ext && p.ext_T != T * spl) return fail(FWI_ERR_STATE, "extended-image ring differs from the graph chunk");
   int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
   const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
                                       (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
@@ -612,7 +624,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
       ExtArgs ec = e;
       ec.step_ctr = ctr;
       ec.step0 = 0;
-      ec.count = T;
+      ec.count = T * spl;
       le = launch_ext_image(ec, cs);
     }
     if (le == hipSuccess) le = launch_advance(ctr, T, cs);
@@ -640,9 +652,10 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
     a.step = k;
     HIP_TRY(launch(a, stream));
   }
-  if (ext && nsteps > full * T) {
-    e.step0 = full * T;
-    e.count = nsteps - full * T;
+  if (ext && nsteps > full * T) {  // the remaining time steps, one window
+    e.step_ctr = nullptr;
+    e.step0 = full * T * spl;
+    e.count = total_steps - e.step0;
     HIP_TRY(launch_ext_image(e, stream));
   }
   return FWI_OK;

@@ -105,16 +105,18 @@ def test_ragged_1024x384_extremes_batched(steps):
     assert np.all(tr[:geom2.rec_ptr[1], int(geom2.nt[0]):] == 0)
 
 
-def test_layered_1024x384_extended_image():
+@pytest.mark.parametrize("steps", [1, 2])
+def test_layered_1024x384_extended_image(steps):
     """Offset-extended image |h| <= 16 at full grid size: 8 shots (the 2
     stored ones repeated 4 times) in one batch of 8 slots with graph chunks,
-    so the result is 4x the oracle's; every 4th offset slice is compared."""
+    so the result is 4x the oracle's; every 4th offset slice is compared.
+    With one or two time steps per forward and reverse launch."""
     name = "layered_1024x384_nt400_ext16"
     z, w, grid, geom2, wav, d2 = golden(name)
     geom = geom2.subset([0, 1] * 4)
     d_obs = np.concatenate([d2] * 4)
     hmax, hs, zs = int(z["hmax"]), int(z["hs"]), int(z["zs"])
-    ex = B.make_exec(shots_in_flight=8, tile_rows=16, graph_steps=32)
+    ex = B.make_exec(shots_in_flight=8, tile_rows=16, graph_steps=32, reverse_steps=steps, forward_steps=steps)
     J, g, image = B.extended_image(w.v_start, wav, grid, geom, d_obs, hmax, "int", ex)
     assert report("layered nt400 ext J", abs(float(J) - 4 * float(z["J"])) / (4 * float(z["J"])), TRACE_TOL) \
         <= TRACE_TOL
