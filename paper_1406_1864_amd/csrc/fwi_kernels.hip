@@ -782,8 +782,9 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
   // rings indexed by sweep position p at slot (p + 4) % W
   float uc[W], lc[W];         // A's inputs u[m-1], lam[m+1]: positions j-4 .. j+5
   float uo[W], lo[W], dA[W];  // A's results u[m-2], lam[m], D of step m: positions j-9 .. j
-  float uh[R], lh[R], p0[R], pl[R], pw[R], sa[R];  // A's halo columns, point-wise operands, strip value
-  float wB[R], gB[R], eB[R], sb[R];                // B's point-wise operands, strip value
+  float wr[W];  // w: positions j-4 .. j+PF (B uses A's loads 4 rows later)
+  float uh[R], lh[R], p0[R], pl[R], sa[R];  // A's halo columns, point-wise operands, strip value
+  float gB[R], eB[R], sb[R];                // B's point-wise operands, strip value
   // every row issues the same loads (strip values: every row of a tile at
   // the ring): stencil rows just outside the grid read the zero guard rows,
   // point-wise rows are clamped into the grid (rows past it are never used)
@@ -800,10 +801,9 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
     w = bld(rW, oc, rc * P4);
     if (ring) st = bld(rS, strip_off(rc), osA);
   };
-  auto load_ptB = [&](int r, float& w, float& g, float& e, float& st) {
+  auto load_ptB = [&](int r, float& g, float& e, float& st) {
     const int rc = clamp_row(d, r);
     const int32_t mo = mrow4(rc);
-    w = bld(rW, oc, rc * P4);
     g = bld(rG, om, mo);
     e = bld(rG, om, mo + oE);
     if (ring) st = bld(rS, strip_off(rc), osB);
@@ -815,12 +815,12 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
 #pragma unroll
   for (int j = 0; j < R; ++j) sa[j] = sb[j] = 0.0f;
 #pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    load_ptA(zA0 + dz * j, uh[j], lh[j], p0[j], pl[j], pw[j], sa[j]);
-    load_ptB(zA0 - dz * (kRadius - j), wB[j], gB[j], eB[j], sb[j]);
-  }
+  for (int j = 0; j < W; ++j) uo[j] = lo[j] = dA[j] = wr[j] = 0.0f;
 #pragma unroll
-  for (int j = 0; j < W; ++j) uo[j] = lo[j] = dA[j] = 0.0f;
+  for (int j = 0; j < PF; ++j) {
+    load_ptA(zA0 + dz * j, uh[j], lh[j], p0[j], pl[j], wr[(j + 4) % W], sa[j]);
+    load_ptB(zA0 - dz * (kRadius - j), gB[j], eB[j], sb[j]);
+  }
 
   for (int jb = 0; jb < nA; jb += W) {
     static_for<W>([&](auto rc) __attribute__((always_inline)) {
@@ -831,8 +831,8 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
       load_win(z + dz * (kRadius + PF), uc[(r + 8 + PF) % W], lc[(r + 8 + PF) % W]);
       {
         const int qn = (r + PF) % R;
-        load_ptA(z + dz * PF, uh[qn], lh[qn], p0[qn], pl[qn], pw[qn], sa[qn]);
-        load_ptB(z - dz * (kRadius - PF), wB[qn], gB[qn], eB[qn], sb[qn]);
+        load_ptA(z + dz * PF, uh[qn], lh[qn], p0[qn], pl[qn], wr[(r + 4 + PF) % W], sa[qn]);
+        load_ptB(z - dz * (kRadius - PF), gB[qn], eB[qn], sb[qn]);
       }
       const int sA = (r + 4) % W;  // ring slot of row z
       const int sB = r % W;        // ring slot of row z - 4
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
       float lapL = laplace<W>(lc, r + 4, xr[1] + kWave * wv, lane);
       float lapU = laplace<W>(uc, r + 4, xr[0] + kWave * wv, lane);
       {
-        const float w = pw[qa], cu = uc[sA], cl = lc[sA];
+        const float w = wr[sA], cu = uc[sA], cl = lc[sA];
         float lo_ = 0.0f, uo_ = 0.0f, d_ = 0.0f;
         if (tile_int && z >= mz_lo && z < mz_hi && z != rzA && z != src_row) {
           lo_ = fmaf(w, lapL, 2.0f * cl - pl[qa]);
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
         const int qb = r % R;
         float lapLB = laplace<W>(lo, r, xr[3] + kWave * wv, lane);
         float lapUB = laplace<W>(uo, r, xr[2] + kWave * wv, lane);
-        const float w = wB[qb], cu = uo[sB], cl = lo[sB], pu = uc[sB], pl1 = lc[sB], da = dA[sB];
+        const float w = wr[sB], cu = uo[sB], cl = lo[sB], pu = uc[sB], pl1 = lc[sB], da = dA[sB];
         float l1 = 0.0f, u1 = 0.0f, gn = 0.0f, en = 0.0f, dB = 0.0f;
         bool st_l = own_col, st_u = own_col, st_g = own_col;
         if (tile_int && zbB >= mz_lo && zbB < mz_hi && zbB != rzB && zbB != src_row && hasB) {
@@ -1084,22 +1084,20 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
   // rings indexed by sweep position p at slot (p + 4) % W
   float uc[W];          // A's input u[n]: positions j-4 .. j+5
   float uo[W], dq[W];   // A's results u[n+1], d[n+1]: positions j-9 .. j
-  float uh[R], pd[R], pw[R];  // A's halo column, d[n], w
-  float wB[R];                // B's w
+  float wr[W];          // w: positions j-4 .. j+PF (B uses A's loads 4 rows later)
+  float uh[R], pd[R];   // A's halo column, d[n]
   auto load_ptA = [&](int r, float& hu, float& dn, float& w) {
     hu = bld(rU, oh, ouIn + r * P4);
     const int rc = clamp_row(d, r);
     dn = bld(rU, oc, odIn + rc * P4);
     w = bld(rW, oc, rc * P4);
   };
-  auto load_ptB = [&](int r, float& w) { w = bld(rW, oc, clamp_row(d, r) * P4); };
 #pragma unroll
   for (int j = 0; j < 8 + PF; ++j) uc[j] = bld(rU, oc, ouIn + (zA0 + dz * (j - kRadius)) * P4);
 #pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    load_ptA(zA0 + dz * j, uh[j], pd[j], pw[j]);
-    load_ptB(zA0 - dz * (kRadius - j), wB[j]);
-  }
+  for (int j = 0; j < W; ++j) wr[j] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < PF; ++j) load_ptA(zA0 + dz * j, uh[j], pd[j], wr[(j + 4) % W]);
 #pragma unroll
   for (int j = 0; j < W; ++j) uo[j] = dq[j] = 0.0f;
 
@@ -1112,8 +1110,7 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
       uc[(r + 8 + PF) % W] = bld(rU, oc, ouIn + (z + dz * (kRadius + PF)) * P4);
       {
         const int qn = (r + PF) % R;
-        load_ptA(z + dz * PF, uh[qn], pd[qn], pw[qn]);
-        load_ptB(z - dz * (kRadius - PF), wB[qn]);
+        load_ptA(z + dz * PF, uh[qn], pd[qn], wr[(r + 4 + PF) % W]);
       }
       const int sA = (r + 4) % W, sB = r % W, qa = r % R;
       float(*xr)[LR] = xrow[r & 1];
@@ -1126,7 +1123,7 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
       // ---- step A at row z
       {
         float lap = laplace<W>(uc, r + 4, xr[0] + kWave * wv, lane);
-        const float c = uc[sA], dn = pd[qa], w = pw[qa];
+        const float c = uc[sA], dn = pd[qa], w = wr[sA];
         float out = 0.0f, dnew = 0.0f;
         const bool own_row = z >= z0 && z < z1;
         if (tile_int && z >= mz_lo && z < mz_hi && z != rzA && z != src_row && !saveA) {
@@ -1175,7 +1172,7 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
       const int zbB = z - dz * kRadius;
       if (hasB && j >= 2 * kRadius) {
         float lap = laplace<W>(uo, r, xr[1] + kWave * wv, lane);
-        const float c = uo[sB], dn = dq[sB], w = wB[r % R];
+        const float c = uo[sB], dn = dq[sB], w = wr[sB];
         float out, dnew;
         if (tile_int && zbB >= mz_lo && zbB < mz_hi && zbB != rzB && zbB != src_row && !saveB) {
           dnew = fmaf(w, lap, dn);
