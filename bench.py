@@ -97,7 +97,8 @@ def kernel_hash():
 def measured_traffic(kname, chosen):
     """HBM bytes per launch of `kname` from the committed rocprofv3 counter
     summary (FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy), or None when that
-    summary was taken on other kernel source or another launch configuration."""
+    summary was taken on other kernel source or with other settings of the
+    reverse launches (the forward settings leave that kernel's bytes alone)."""
     path = os.path.join(ROOT, "profiles", f"{kname}_pmc_layered_1024x384.json")
     if not os.path.exists(path):
         return None
@@ -105,8 +106,8 @@ def measured_traffic(kname, chosen):
         p = json.load(fh)
     if p.get("kernel_source_sha") != kernel_hash():
         return None
-    keys = ("shots_in_flight", "tile_rows", "graph_steps", "prefetch", "prefetch_reverse",
-            "shots_in_flight_reverse", "tile_rows_reverse", "reverse_steps", "forward_steps")
+    keys = ("graph_steps", "prefetch_reverse", "shots_in_flight_reverse", "tile_rows_reverse",
+            "reverse_steps")
     if any(p["launch_config"].get(k) != chosen.get(k) for k in keys):
         return None
     return p.get("bytes_per_launch")

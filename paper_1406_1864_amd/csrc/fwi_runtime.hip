@@ -920,6 +920,13 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   // fields from the Infinity Cache more than over a whole sweep.
   std::stable_sort(Rv.begin(), Rv.end(),
                    [](const Cand& x, const Cand& y) { return x.rs > y.rs || (x.rs == y.rs && x.S > y.S); });
+  // the same for the forward: two steps per launch, more shots, then longer
+  // bands (fewer halo rows read twice)
+  std::stable_sort(F.begin(), F.end(), [](const Cand& x, const Cand& y) {
+    if (x.fs != y.fs) return x.fs > y.fs;
+    if (x.S != y.S) return x.S > y.S;
+    return x.TZ > y.TZ;
+  });
   // the pair with the least time per shot, the reverse's shots in flight
   // dividing the forward's (any size in the autograd split); a later pair
   // must be 2 % faster to replace one
