@@ -10,4 +10,5 @@ from .acoustic import (C8, CFL_LIMIT, Propagator, laplacian, sponge_gamma, padde
                        gradient_eq3_literal, end_of_record_term)
 from .hessian import (aperture_factor, offset_diag, shot_scaling, offset_scaling,
                       precondition, extended_born_columns, offset_diag_exact, extended_image,
-                      born_shot, born, gn_hvp)
+                      born_shot, born, gn_hvp, spectral_bins, green_series,
+                      source_series, power, offset_diag_spectral)

@@ -23,6 +23,13 @@ Readings taken where the paper is silent or garbled:
   X_min,s / X_max,s the extreme receiver x-positions (metres) of shot s and
   z_y = max((iz_y - iz_rec,s) h, h/2) measured from the shallowest receiver
   of the shot; ``rcv_model='none'`` uses A_s = 1 (the Shin form).
+* the exact receiver term (``offset_diag_spectral``): the same diagonal with
+  sum_r |G(x-h, r, omega)|^2 in place of the aperture factor, summed over the
+  bins of L = 2 nt point DFTs of the discrete series (source side: D[j]/dt^2,
+  j = 1 .. nt-1; receiver side: the impulse response of the scheme from the
+  receiver, n = 0 .. nt-2, by reciprocity); with every bin it equals the
+  extended-Born column norms over the whole response, not cut at the record's
+  end.  A band limit fmax keeps the bins up to fmax.
 * preconditioners: P_shot = (4/v^6) H1, P_off(x) = sum_h D(x, h),
   g_prec = g / (P + eps max P) with eps = 1e-2.
 """
@@ -238,3 +245,97 @@ def gn_hvp(v, grid, geom, wavelet, dv, kind, shots=None):
         Jb += Js
         G += Gs
     return Jb, 2.0 / v ** 3 * G
+
+
+# --------------------------------------------------------------------------
+# the offset diagonal with the exact receiver term (frequency domain)
+# --------------------------------------------------------------------------
+def spectral_bins(nt, dt, fmax=None):
+    """DFT length L = 2 nt and the bins k = 0 .. K-1 kept, with their one-sided
+    weights: a real series of L samples has sum_t x^2 = (1/L) sum_k m_k |X_k|^2,
+    m_0 = m_{L/2} = 1, m_k = 2 in between.  fmax (Hz) keeps the bins with
+    k / (L dt) <= fmax; None keeps all of them (the identity is then exact)."""
+    L = 2 * int(nt)
+    K = L // 2 + 1
+    if fmax is not None:
+        K = min(K, int(np.floor(fmax * L * dt + 1e-9)) + 1)
+    m = np.full(K, 2.0)
+    m[0] = 1.0
+    if K == L // 2 + 1:
+        m[-1] = 1.0
+    return L, K, m
+
+
+def green_series(v, grid, iz, ix, nt):
+    """B(n, y) = h^2 u[n+1](y) on the model cells, n = 0 .. nt-2: the wavefield
+    of a unit source term injected at (iz, ix) in the first update (a forward
+    run with the wavelet [1, 0, 0, ...], which enters as 1/h^2).  The scheme is
+    symmetric (a diagonal time operator plus the symmetric Laplacian), so
+    B(n, y) is also the response at (iz, ix) n updates after a unit source
+    term at y: the receiver-side Green's function of a receiver there."""
+    N, nz, nx = grid.nsponge, grid.nz, grid.nx
+    imp = np.zeros(nt)
+    imp[0] = 1.0
+    hist = []
+    none = np.zeros(0, np.int64)
+    forward(v, grid, (iz, ix, none, none, nt), imp, keep=hist)     # hist[n+1] = u[n]
+    return np.array(hist[2:])[:, N:N + nz, N:N + nx] * grid.dx ** 2  # u[1] .. u[nt-1]
+
+
+def source_series(v, grid, shot, wavelet):
+    """A(i, y) = D[i+1](y) / dt^2 on the model cells, i = 0 .. nt-2, with
+    D[j] = u[j] - 2u[j-1] + u[j-2]: the series the extended Born operator of
+    eq. (5) injects (times 2/v^3)."""
+    N, nz, nx = grid.nsponge, grid.nz, grid.nx
+    hist = []
+    forward(v, grid, shot, wavelet, keep=hist)
+    u = np.array(hist)[:, N:N + nz, N:N + nx]                        # u[-1] .. u[nt-1]
+    return (u[2:] - 2.0 * u[1:-1] + u[:-2]) / grid.dt ** 2
+
+
+def power(series, L, K):
+    """|X_k|^2, k = 0 .. K-1, of the L-point DFT along axis 0 (zero padded)."""
+    X = np.fft.rfft(series, n=L, axis=0)[:K]
+    return X.real ** 2 + X.imag ** 2
+
+
+def offset_diag_spectral(v, grid, geom, wavelet, hmax, fmax=None, shots=None):
+    """Diagonal of the subsurface-offset Hessian (section 3, y = x and
+    h_bar = h) with the exact receiver term in place of the aperture factor:
+
+        D(x, h) = (4 / v(x)^6) sum_s sum_{r in R_s} (1/L) sum_k m_k
+                  |A_s_hat(x + h, k)|^2 |B_r_hat(x - h, k)|^2,
+
+    the frequency-domain form of the paper's diagonal (source energy at x+h
+    times the receiver Green's functions at x-h, frequency by frequency), on
+    L = 2 nt point DFTs of the series ``source_series`` (A) and
+    ``green_series`` (B), with the bins of ``spectral_bins``.  With every bin this is, by Parseval,
+    sum_{s,r,t} c^2 over the extended-Born column of (x, h) convolved over the
+    whole response (not cut at the record's end); for a record long enough to
+    hold the response it is diag(J_ext^T J_ext) of the conventional misfit.
+    Offsets are horizontal, zero where x+h or x-h leaves the model.  Returns
+    D[2 hmax + 1][nz][nx]."""
+    v = np.asarray(v, np.float64)
+    nz, nx = v.shape
+    shots = range(geom.nshot) if shots is None else shots
+    D = np.zeros((2 * hmax + 1, nz, nx))
+    green = {}
+    for s in shots:
+        shot = geom.shot(s)
+        riz, rix, nt = shot[2], shot[3], int(shot[4])
+        L, K, m = spectral_bins(nt, grid.dt, fmax)
+        w = np.asarray(wavelet[s] if np.ndim(wavelet) == 2 else wavelet, np.float64)
+        PA = power(source_series(v, grid, shot, w), L, K)
+        PB = np.zeros_like(PA)
+        for r in range(len(riz)):
+            key = (int(riz[r]), int(rix[r]), nt, K)
+            if key not in green:
+                green[key] = power(green_series(v, grid, key[0], key[1], nt), L, K)
+            PB += green[key]
+        for h in range(-hmax, hmax + 1):
+            lo, hi = abs(h), nx - abs(h)
+            if lo >= hi:
+                continue
+            xs = np.arange(lo, hi)
+            D[h + hmax][:, xs] += np.einsum("k,kzx,kzx->zx", m, PA[:, :, xs + h], PB[:, :, xs - h]) / L
+    return D * (4.0 / v ** 6)[None]

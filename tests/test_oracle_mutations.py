@@ -203,3 +203,40 @@ def test_free_surface_mirror_sign_is_caught(monkeypatch):
         return g
     monkeypatch.setattr(ac.Propagator, "mirror", even)
     fails(P.test_free_surface_is_the_antisymmetric_image)
+
+
+def test_two_sided_bin_weights_dropped_are_caught(monkeypatch):
+    """Every bin weighted 1 (the negative frequencies forgotten)."""
+    orig = hs.spectral_bins
+
+    def flat(nt, dt, fmax=None):
+        L, K, m = orig(nt, dt, fmax)
+        return L, K, np.ones_like(m)
+    plant(monkeypatch, hs, "spectral_bins", flat)
+    fails(P.test_spectral_bins_are_parseval)
+    fails(P.test_offset_diag_spectral_is_full_response_column_norm)
+
+
+def test_green_series_one_step_early_is_caught(monkeypatch):
+    """u[n] instead of u[n+1] for the receiver impulse response."""
+    def early(v, grid, iz, ix, nt):
+        N, nz, nx = grid.nsponge, grid.nz, grid.nx
+        imp = np.zeros(nt)
+        imp[0] = 1.0
+        hist = []
+        none = np.zeros(0, np.int64)
+        ac.forward(v, grid, (iz, ix, none, none, nt), imp, keep=hist)
+        return np.array(hist[1:-1])[:, N:N + nz, N:N + nx] * grid.dx ** 2
+    plant(monkeypatch, hs, "green_series", early)
+    fails(P.test_extended_born_column_is_receiver_impulse_convolution)
+
+
+def test_spectral_offset_sides_swapped_are_caught(monkeypatch):
+    """Source side read at x-h, receiver side at x+h."""
+    orig = hs.offset_diag_spectral
+
+    def swapped(v, grid, geom, wavelet, hmax, fmax=None, shots=None):
+        D = orig(v, grid, geom, wavelet, hmax, fmax, shots)
+        return D[::-1].copy()  # D(x, -h)
+    plant(monkeypatch, hs, "offset_diag_spectral", swapped)
+    fails(P.test_offset_diag_spectral_is_full_response_column_norm)

@@ -627,3 +627,86 @@ def test_preconditioner_water_level():
     assert np.allclose(out, g / (P + 2.0), rtol=1e-15, atol=0.0)
     v = np.full((2, 2), 2.0)
     assert np.allclose(oracle.shot_scaling(v, P), P / 16.0, rtol=1e-15, atol=0.0)
+
+
+# ------------------------------------------- offset diagonal, exact receiver term
+def long_record_case(nt=600, nsponge=16):
+    """10x14 cells, a Gaussian anomaly, two shots with 3 and 2 receivers,
+    Ricker 15 Hz; with nt = 600 (0.6 s) the response has left the grid."""
+    nz, nx = 10, 14
+    grid = Grid(nz, nx, 10.0, 1e-3, nt, nsponge, 2200.0)
+    v = gaussian_anomaly(nz, nx, 2000.0, 0.1, 2.0, iz0=5, ix0=7).astype(np.float64)
+    geom = Geometry(np.array([1, 1], np.int32), np.array([2, 11], np.int32),
+                    np.array([0, 3, 5], np.int32), np.array([1, 1, 1, 1, 1], np.int32),
+                    np.array([1, 5, 12, 3, 8], np.int32), np.array([nt, nt], np.int32))
+    return grid, v, geom, ricker(15.0, 1e-3, nt)
+
+
+DIAG_CELLS = [(5, 7, 0), (3, 4, 1), (8, 10, -2), (2, 6, 2), (6, 3, -1)]
+
+
+def test_spectral_bins_are_parseval():
+    """sum_t x^2 = (1/L) sum_k m_k |X_k|^2 for real series of L = 2 nt samples."""
+    rng = np.random.default_rng(5)
+    for nt in (7, 8, 33):
+        L, K, m = oracle.spectral_bins(nt, 1e-3)
+        assert L == 2 * nt and K == nt + 1
+        x = rng.standard_normal((nt - 1, 3))
+        got = oracle.power(x, L, K).T @ m / L
+        assert np.allclose(got, np.sum(x * x, axis=0), rtol=1e-13, atol=0)
+    L, K, m = oracle.spectral_bins(1000, 1e-3, fmax=60.0)
+    assert (L, K) == (2000, 121) and m[0] == 1 and np.all(m[1:] == 2)
+
+
+def test_extended_born_column_is_receiver_impulse_convolution():
+    """Reciprocity and the time indexing of the series: the extended-Born
+    column of (x, h), modelled by injecting at x-h and recording at r, equals
+    (2/v^3) (B_r(x-h) * A_s(x+h))[m-1] at m = 1 .. nt-1, with B_r the impulse
+    response from the receiver and A_s the source-side series."""
+    grid, v, geom, wav = long_record_case(nt=240, nsponge=8)
+    for s in range(geom.nshot):
+        shot = geom.shot(s)
+        nt = shot[4]
+        cols = oracle.extended_born_columns(v, grid, shot, wav, DIAG_CELLS)
+        A = oracle.source_series(v, grid, shot, wav)
+        for r in range(len(shot[2])):
+            B = oracle.green_series(v, grid, int(shot[2][r]), int(shot[3][r]), nt)
+            for c, (iz, ix, h) in enumerate(DIAG_CELLS):
+                conv = np.convolve(B[:, iz, ix - h], A[:, iz, ix + h])[:nt - 1] * 2.0 / v[iz, ix] ** 3
+                ref = cols[c, r]
+                assert ref[0] == 0.0
+                assert np.max(np.abs(ref[1:] - conv)) <= 1e-10 * np.max(np.abs(conv))
+
+
+def test_offset_diag_spectral_is_full_response_column_norm():
+    """With every bin: (4/v^6) sum_{s,r} sum_t ((B_r * A_s)(t))^2 over the
+    whole linear convolution (time domain, no DFT)."""
+    grid, v, geom, wav = long_record_case(nt=240, nsponge=8)
+    D = oracle.offset_diag_spectral(v, grid, geom, wav, 2)
+    ref = np.zeros(len(DIAG_CELLS))
+    for s in range(geom.nshot):
+        shot = geom.shot(s)
+        A = oracle.source_series(v, grid, shot, wav)
+        for r in range(len(shot[2])):
+            B = oracle.green_series(v, grid, int(shot[2][r]), int(shot[3][r]), shot[4])
+            for c, (iz, ix, h) in enumerate(DIAG_CELLS):
+                cc = np.convolve(B[:, iz, ix - h], A[:, iz, ix + h])
+                ref[c] += 4.0 / v[iz, ix] ** 6 * np.sum(cc * cc)
+    got = np.array([D[h + 2, iz, ix] for iz, ix, h in DIAG_CELLS])
+    assert np.max(np.abs(got / ref - 1.0)) < 1e-10
+    # offsets that leave the model contribute nothing
+    assert np.all(D[0, :, :2] == 0) and np.all(D[4, :, -2:] == 0)
+
+
+def test_offset_diag_spectral_matches_jacobian_columns_on_a_long_record():
+    """When the response has left the grid before the record ends, the exact
+    diagonal diag(J_ext^T J_ext) of the conventional misfit (explicit columns,
+    cut at the record's end) and the spectral form agree; the band limit of
+    four times the Ricker peak changes nothing that matters."""
+    grid, v, geom, wav = long_record_case(nt=600, nsponge=16)
+    D = oracle.offset_diag_spectral(v, grid, geom, wav, 2)
+    ex = oracle.offset_diag_exact(v, grid, geom, wav, DIAG_CELLS, "l2")
+    got = np.array([D[h + 2, iz, ix] for iz, ix, h in DIAG_CELLS])
+    assert np.max(np.abs(got / ex - 1.0)) < 2e-4
+    Db = oracle.offset_diag_spectral(v, grid, geom, wav, 2, fmax=60.0)
+    assert np.max(np.abs(Db - D)) <= 1e-6 * np.max(D)
