@@ -56,6 +56,10 @@ def parse():
                     help="also time the offset-extended image for |h| <= EXT against the plain gradient call")
     ap.add_argument("--gn", action="store_true",
                     help="also time the Gauss-Newton Hessian-vector product against the plain gradient call")
+    ap.add_argument("--exact-diag", type=int, default=0,
+                    help="also time the offset diagonal with the exact receiver term on the first "
+                         "--exact-shots shots and EXACT_DIAG of their receivers (band to 4 f_peak)")
+    ap.add_argument("--exact-shots", type=int, default=2)
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
                          "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps]")
@@ -186,6 +190,56 @@ def time_gn_hvp(args, grid, geom, w, d_obs, ex, dev):
     return {"value": geom.nshot / res["gn_hvp"], "unit": "shot-products/s", "ms_per_call": 1e3 * res["gn_hvp"],
             "gradient_ms_per_call": 1e3 * res["gradient"],
             "overhead_vs_gradient": res["gn_hvp"] / res["gradient"] - 1.0}
+
+
+FP32_MFMA_PEAK_TFS = 157.3
+
+
+def time_offset_diag_exact(args, grid, geom, w, dev):
+    """fwi_offset_diag_exact on a subset: the first shots and an evenly spread
+    subset of their receivers (one group), band up to 4 f_peak, |h| <= 16.
+    Each run (a receiver's impulse response or a shot) is a forward sweep that
+    captures the model cells' series, then one FP32 GEMM with the DFT matrix;
+    the call's time is split into the two from the per-run costs below."""
+    import torch
+    from paper_1406_1864_amd import binding as B
+    from paper_1406_1864_amd.synthetic import Geometry
+    ns = min(args.exact_shots, geom.nshot)
+    a, b = int(geom.rec_ptr[0]), int(geom.rec_ptr[1])
+    keep = np.linspace(a, b - 1, min(args.exact_diag, b - a)).round().astype(np.int64)
+    sub = Geometry(geom.src_iz[:ns].copy(), geom.src_ix[:ns].copy(),
+                   (np.arange(ns + 1) * len(keep)).astype(np.int32),
+                   np.tile(geom.rec_iz[keep], ns), np.tile(geom.rec_ix[keep], ns), geom.nt[:ns].copy())
+    hmax, fmax = 16, 4.0 * w.f_peak
+    ex = B.make_exec(shots_in_flight=int(os.environ.get("FWI_EXACT_SIF", "1")))
+    nbytes = B.fwi_offset_diag_exact_workspace_bytes(grid, sub, ex, hmax, fmax)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    fn = lambda: B.offset_diag_exact(w.v_start, w.wavelet, grid, sub, hmax, fmax, ex, ws=ws, device=dev)
+    D = fn()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(D).all())
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    call = (time.perf_counter() - t0) / args.steps
+    runs = ns + len(keep)
+    nt = int(sub.nt[0])
+    L = 2 * nt
+    K = min(L // 2 + 1, int(np.floor(fmax * L * grid.dt + 1e-9)) + 1)
+    model = grid.nz * grid.nx
+    Z, X = grid.padded
+    gemm_flop = 2.0 * model * (nt - 1) * 2 * K          # per run
+    full_runs = w.geom.nshot + (b - a)
+    return {"value": runs / call, "unit": "runs/s (forward sweep with series capture + DFT GEMM)",
+            "shots": ns, "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K,
+            "nt": nt, "ms_per_call": 1e3 * call, "ms_per_run": 1e3 * call / runs,
+            "gemm_tflop_per_run": gemm_flop / 1e12,
+            "gemm_shape_per_run": [model, 2 * K, nt - 1],
+            "cell_updates_per_run": float(Z * X * (nt - 1)),
+            "workspace_gb": nbytes / 1e9,
+            "full_problem_s_extrapolated": full_runs * call / runs,
+            "full_problem_runs": full_runs}
 
 
 def main():
@@ -381,6 +435,8 @@ def main():
         out["extended_image"] = time_extended_image(args, grid, geom, w, d_obs, ex, dev)
     if args.gn:
         out["gn_hvp"] = time_gn_hvp(args, grid, geom, w, d_obs, ex, dev)
+    if args.exact_diag > 0:
+        out["offset_diag_exact"] = time_offset_diag_exact(args, grid, geom, w, dev)
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded

@@ -305,6 +305,37 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
                         int hmax, int rcv_model, float *offset_diag,
                         void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Diagonal of the subsurface-offset Hessian with the exact receiver term
+ * (section 3: the diagonal part y = x, h_bar = h of the offset Hessian,
+ * frequency by frequency, with the receiver Green's functions themselves in
+ * place of the aperture factor that fwi_hessian_diag's FWI_HESS_OFFSET uses):
+ *
+ *   diag[h + hmax][z][x] = (4 / v^6) h_g^4 / (dt^4 L) sum_s sum_{r in R_s}
+ *                          sum_k m_k |A_s(x + h, k)|^2 |B_r(x - h, k)|^2
+ *
+ * with L = 2 nt point DFTs (zero padded) of the discrete series
+ *   A_s(y, j) = u[j+1] - 2 u[j] + u[j-1] at y (shot s, j = 0 .. nt-2),
+ *   B_r(y, n) = u[n+1] at y of a run whose wavelet is [1, 0, 0, ...] with
+ *               its source at receiver r (by reciprocity of the scheme, the
+ *               response at r to a unit source term at y), n = 0 .. nt-2,
+ * h_g the grid spacing, m_0 = 1, m_k = 2, and m = 1 for the Nyquist bin
+ * k = nt.  fmax > 0 keeps the bins k <= fmax L dt (frequencies up to fmax
+ * Hz); fmax = 0 keeps all nt + 1 of them.  With every bin this is the norm of
+ * the extended-Born column of (x, h) over the whole response (conventional
+ * misfit).  Horizontal offsets |h| <= hmax <= 32; terms with x+h or x-h
+ * outside the model are 0.  Shots are grouped by (record length, receiver
+ * set); each group costs one forward run per receiver and per shot, and the
+ * workspace holds the model cells' series of shots_in_flight runs (default 8)
+ * and their spectra: see fwi_offset_diag_exact_workspace_bytes.  Not with a
+ * free surface.  diag: device [2 hmax + 1][nz][nx], overwritten.  The DFT is
+ * a GEMM through rocBLAS (FP32). */
+size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
+                                             const fwi_exec *exec, int hmax, double fmax);
+int fwi_offset_diag_exact(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                          const float *v, const float *wavelet, int64_t wavelet_stride,
+                          int hmax, double fmax, float *diag,
+                          void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Preconditioned gradient (section 3.1): out = grad / (P + eps * max P) with
  * P = (4/v^6) * hdiag (kind SHOT, hdiag = H1 [nz][nx]) or
  * P = sum_h hdiag[h] (kind OFFSET, hdiag = D [2*hmax+1][nz][nx]).

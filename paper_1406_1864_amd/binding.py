@@ -100,6 +100,11 @@ _SIGS = {
     "fwi_misfit_backward": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                     c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
+    "fwi_offset_diag_exact_workspace_bytes": (c_size_t, [POINTER(fwi_grid), POINTER(fwi_geometry),
+                                                         POINTER(fwi_exec), c_int, ctypes.c_double]),
+    "fwi_offset_diag_exact": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
+                                      c_void_p, c_int64, c_int, ctypes.c_double, c_void_p, c_void_p, c_size_t,
+                                      c_void_p]),
     "fwi_precondition": (c_int, [POINTER(fwi_grid), c_void_p, c_void_p, c_int, c_void_p, c_int, c_float,
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_status": (c_int, [c_void_p, c_void_p]),
@@ -285,6 +290,20 @@ def fwi_misfit_backward(grid, geom, exec_, v, wavelet, wavelet_stride, grad_scal
                                              _ptr(workspace), int(ws_bytes), _stream(stream)))
 
 
+def fwi_offset_diag_exact_workspace_bytes(grid, geom, exec_, hmax, fmax) -> int:
+    g, G = make_grid(grid), _geo(geom)
+    return int(load().fwi_offset_diag_exact_workspace_bytes(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_),
+                                                            int(hmax), float(fmax)))
+
+
+def fwi_offset_diag_exact(grid, geom, exec_, v, wavelet, wavelet_stride, hmax, fmax, diag, workspace, ws_bytes,
+                          stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_offset_diag_exact(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v),
+                                               _ptr(wavelet), int(wavelet_stride), int(hmax), float(fmax),
+                                               _ptr(diag), _ptr(workspace), int(ws_bytes), _stream(stream)))
+
+
 def fwi_precondition(grid, v, grad, kind, hdiag, hmax, eps, out, workspace, ws_bytes, stream=None):
     g = make_grid(grid)
     return _check(load().fwi_precondition(ctypes.byref(g), _ptr(v), _ptr(grad), int(kind), _ptr(hdiag),
@@ -431,6 +450,23 @@ def hessian_diag(v, wavelet, grid, geom, kind=HESS_EQ1, hmax=0, rcv_model="pm", 
     out = torch.empty(shape, dtype=torch.float32, device=device)
     ws = workspace(grid, G, WS_HESSIAN, exec_, hmax, device=device) if ws is None else ws
     fwi_hessian_diag(grid, G, exec_, vd, w, ws_, kind, hmax, rcv_model, out, ws, ws.numel())
+    return out
+
+
+def offset_diag_exact(v, wavelet, grid, geom, hmax, fmax=0.0, exec_=None, ws=None, device="cuda"):
+    """Offset diagonal with the exact receiver term, D[2 hmax + 1][nz][nx]
+    (fmax in Hz bounds the frequency band, 0 keeps every bin)."""
+    torch = _torch()
+    G = _geo(geom)
+    vd = _dev(v, torch.float32, device)
+    w, ws_ = _wavelet(wavelet, grid.nt_max, device)
+    out = torch.empty((2 * hmax + 1, grid.nz, grid.nx), dtype=torch.float32, device=device)
+    if ws is None:
+        n = fwi_offset_diag_exact_workspace_bytes(grid, G, exec_, hmax, fmax)
+        if n == 0:
+            raise FwiError(FWI_ERR_ARG, last_error())
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
+    fwi_offset_diag_exact(grid, G, exec_, vd, w, ws_, hmax, fmax, out, ws, ws.numel())
     return out
 
 

@@ -21,7 +21,9 @@ def build(verbose=False):
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            # packed FP32 instructions are kept out of the generated code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I" + os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES
+           "-I" + os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES + [
+           # the DFT of the exact offset diagonal's series is a plain GEMM
+           "-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -112,6 +112,10 @@ struct StepArgs {
   // Born modelling (forward sweep only): the perturbation wavefield
   float* bu;            // [cs][3][field]  du[n] at level n & 1, its increment at level 2
   const float* bw;      // 2 dv / v on the padded grid (zero outside the model)
+  // series capture (forward sweep, kFwdCapD / kFwdCapU): the model cells'
+  // value of update n goes to cap[slot * cap_stride + n * model + cell]
+  float* cap;
+  int64_t cap_stride;
 };
 
 // Extended imaging over one window of reverse launch steps
@@ -141,7 +145,9 @@ enum : int { kRevExt = 1, kRevImgU = 2 };
 // forward-kernel feature flags
 // kFwdBorn: also step the Born perturbation wavefield and record it instead of u
 // (kFwdFS, the free-surface variant, is chosen by the launcher from Dims::fs)
-enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8, kFwdFS = 16 };
+// kFwdCapD / kFwdCapU: capture D[n+1] = u[n+1] - 2u[n] + u[n-1] (resp. u[n+1])
+// of the model cells at every update (StepArgs::cap)
+enum : int { kFwdRecord = 1, kFwdCkpt = 2, kFwdIllum = 4, kFwdBorn = 8, kFwdFS = 16, kFwdCapD = 32, kFwdCapU = 64 };
 
 struct MisfitArgs {
   const SlotInfo* slots;
@@ -202,6 +208,15 @@ hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const fl
                                const double* scale, double fac, float* grad, const int32_t* err, hipStream_t s);
 hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
                              const int32_t* trace_shot, float* data, hipStream_t s);
+// exact offset diagonal: W[t + c Tn] = cos / sin (2 pi k t / L) for c = 2k / 2k+1,
+// t < Tn, k < K (the DFT matrix of the captured series)
+hipError_t launch_twiddle(float* W, int Tn, int K, int L, hipStream_t s);
+// P[k][cell] += sum over nslots of C[slot][2k][cell]^2 + C[slot][2k+1][cell]^2
+hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, float* P, hipStream_t s);
+// D[h][z][x] += scale / v^6 sum_k m_k PA[k][z][x+h] PB[k][z][x-h] for |h| <= hmax
+// (both columns in the model), m_0 = 1, m_{K-1} = 1 if nyq, else 2
+hipError_t launch_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
+                                const float* v, float scale, float* D, const int32_t* err, hipStream_t s);
 hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int kind,
                           const float* hdiag, int hmax, float eps, float* out, uint32_t* maxbits,
                           hipStream_t s);

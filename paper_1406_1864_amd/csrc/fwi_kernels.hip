@@ -392,6 +392,8 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
           const float D = wv_ * lap;
           E[mi] = (n == 0) ? D * D : fmaf(D, D, E[mi]);
         }
+        if ((FLAGS & (kFwdCapD | kFwdCapU)) && mcell)
+          a.cap[(int64_t)slot * a.cap_stride + (int64_t)n * d.model + mi] = (FLAGS & kFwdCapD) ? wv_ * lap : out;
         if (FLAGS & kFwdCkpt) {
           const int ri = strip_index(row, col);
           if (ri >= 0) strip[ri] = out;
@@ -1654,6 +1656,8 @@ static hipError_t launch_forward_pf(const StepArgs& a, int flags, hipStream_t s)
     case kFwdIllum: forward_fs<kFwdIllum, PF>(a, s); break;
     case kFwdRecord | kFwdBorn: forward_fs<kFwdRecord | kFwdBorn, PF>(a, s); break;
     case kFwdRecord | kFwdCkpt | kFwdBorn: forward_fs<kFwdRecord | kFwdCkpt | kFwdBorn, PF>(a, s); break;
+    case kFwdCapD: forward_fs<kFwdCapD, PF>(a, s); break;
+    case kFwdCapU: forward_fs<kFwdCapU, PF>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1661,6 +1665,7 @@ static hipError_t launch_forward_pf(const StepArgs& a, int flags, hipStream_t s)
 
 hipError_t launch_forward(const StepArgs& a, int flags, int prefetch, hipStream_t s) {
   if ((flags & kFwdBorn) && (!a.bu || !a.bw)) return hipErrorInvalidValue;
+  if ((flags & (kFwdCapD | kFwdCapU)) && !a.cap) return hipErrorInvalidValue;
   switch (prefetch) {
     case 1: return launch_forward_pf<1>(a, flags, s);
     case 3: return launch_forward_pf<3>(a, flags, s);
@@ -1814,6 +1819,102 @@ hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int
                      2 * hmax + 1, out, maxbits);
   hipLaunchKernelGGL(k_precond_apply, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, grad, eps,
                      maxbits, out);
+  return hipGetLastError();
+}
+
+
+// -------------------------------------------------------------------------
+// Offset diagonal with the exact receiver term: the DFT of the captured
+// series is a plain GEMM against W (the host runtime calls the BLAS); these
+// kernels build W, accumulate the power spectra and form the offset sums.
+// -------------------------------------------------------------------------
+__global__ void k_twiddle(float* W, int Tn, int K, int L) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Tn * 2 * K) return;
+  const int t = (int)(i % Tn), c = (int)(i / Tn), k = c >> 1;
+  // the phase k t / L reduced exactly in integers, the angle in double
+  const int64_t r = ((int64_t)k * t) % L;
+  double sn, cs;
+  sincospi(2.0 * (double)r / (double)L, &sn, &cs);
+  W[i] = (float)((c & 1) ? sn : cs);
+}
+
+hipError_t launch_twiddle(float* W, int Tn, int K, int L, hipStream_t s) {
+  const int64_t n = (int64_t)Tn * 2 * K;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, Tn, K, L);
+  return hipGetLastError();
+}
+
+__global__ void k_power_acc(const float* C, int64_t model, int K, int nslots, float* P) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (cell >= model) return;
+  float acc = P[(int64_t)k * model + cell];
+  for (int sl = 0; sl < nslots; ++sl) {
+    const float* c = C + ((int64_t)sl * 2 * K + 2 * k) * model + cell;
+    const float re = c[0], im = c[model];
+    acc = fmaf(re, re, fmaf(im, im, acc));
+  }
+  P[(int64_t)k * model + cell] = acc;
+}
+
+hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, float* P, hipStream_t s) {
+  if (model <= 0 || K <= 0 || nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_power_acc, dim3((unsigned)((model + 255) / 256), (unsigned)K), dim3(256), 0, s, C, model, K,
+                     nslots, P);
+  return hipGetLastError();
+}
+
+// one thread per model cell, the 2 HM + 1 offset sums in registers (offsets
+// above hmax are skipped); PA is read at x + h, PB at x - h along the row
+template <int HM>
+__global__ void k_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
+                                const float* v, float scale, float* D, const int32_t* err) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.y;
+  if (x >= nx || *err) return;
+  const int64_t model = (int64_t)nz * nx;
+  const int64_t row = (int64_t)z * nx;
+  float acc[2 * HM + 1];
+#pragma unroll
+  for (int j = 0; j < 2 * HM + 1; ++j) acc[j] = 0.0f;
+  for (int k = 0; k < K; ++k) {
+    const float mk = (k == 0 || (nyq && k == K - 1)) ? 1.0f : 2.0f;
+    const float* pa = PA + k * model + row;
+    const float* pb = PB + k * model + row;
+#pragma unroll
+    for (int j = 0; j < 2 * HM + 1; ++j) {
+      const int h = j - HM;
+      if (h < -hmax || h > hmax || x + h < 0 || x + h >= nx || x - h < 0 || x - h >= nx) continue;
+      acc[j] = fmaf(mk * pa[x + h], pb[x - h], acc[j]);
+    }
+  }
+  const float iv = 1.0f / v[row + x];
+  const float iv2 = iv * iv;
+  const float f = scale * iv2 * iv2 * iv2;
+#pragma unroll
+  for (int j = 0; j < 2 * HM + 1; ++j) {
+    const int h = j - HM;
+    if (h < -hmax || h > hmax) continue;
+    float* out = D + (int64_t)(h + hmax) * model + row + x;
+    *out += f * acc[j];
+  }
+}
+
+hipError_t launch_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
+                                const float* v, float scale, float* D, const int32_t* err, hipStream_t s) {
+  if (nz <= 0 || nx <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((nx + 127) / 128), (unsigned)nz), block(128);
+  if (hmax <= 4)
+    hipLaunchKernelGGL(k_diag_products<4>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+  else if (hmax <= 8)
+    hipLaunchKernelGGL(k_diag_products<8>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+  else if (hmax <= 16)
+    hipLaunchKernelGGL(k_diag_products<16>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+  else if (hmax <= 32)
+    hipLaunchKernelGGL(k_diag_products<32>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

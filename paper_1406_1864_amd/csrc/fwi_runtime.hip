@@ -11,6 +11,7 @@
 // those inputs; captured graphs are cached inside their plan, keyed by the
 // device pointers they bake in.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -152,6 +153,8 @@ struct Plan {
   int fwd_steps = 1;           // time steps per launch of the gradient's forward sweep (1 or 2)
   int ulevels = kULevels, llevels = kLamLevels;
   int XT2 = 0;                 // tiles of the two-step reverse sweep along x
+  float* cap = nullptr;        // series capture of the forward sweep (exact offset diagonal)
+  int64_t cap_stride = 0;
   double sp_a = 0.0;
   double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -522,6 +525,8 @@ StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* w
   a.ext_T = p.ext_T;
   a.bu = p.born ? at<float>(ws, p.L.bu) + p.d.guard : nullptr;
   a.bw = p.born ? at<float>(ws, p.L.bw) : nullptr;
+  a.cap = p.cap;
+  a.cap_stride = p.cap_stride;
   return a;
 }
 
@@ -1160,6 +1165,159 @@ int ws_check(const Plan& p, size_t ws_bytes) {
   return FWI_OK;
 }
 
+
+// ------------------------------------------------- exact offset diagonal
+// Shots are grouped by (record length, receiver set): a group's receiver term
+// sum_r |G_r|^2 is one power spectrum.  Each group runs the receivers'
+// impulse responses and then its shots as batches of forward sweeps that
+// capture the model cells' series; a GEMM with the DFT matrix gives the
+// spectra, whose powers are summed per side; the offset sums follow.
+struct DxGroup {
+  int nt = 0;
+  std::vector<int> shots;
+  std::vector<int32_t> riz, rix;  // the receiver set (with repeats), sorted
+};
+
+struct DxLayout {
+  int S = 0;              // series in flight
+  size_t plan = 0;        // plan region (offset 0)
+  size_t cap = 0, C = 0, PA = 0, PB = 0, W = 0, imp = 0, wav = 0, total = 0;
+  int Tn = 0, K = 0;      // largest series length and bin count
+};
+
+void dx_bins(int nt, double dt, double fmax, int& L, int& K, int& nyq) {
+  L = 2 * nt;
+  K = L / 2 + 1;
+  if (fmax > 0) K = std::min(K, (int)std::floor(fmax * L * dt + 1e-9) + 1);
+  nyq = (K == L / 2 + 1);
+}
+
+std::vector<DxGroup> dx_groups(const fwi_grid* g, const fwi_geometry* geo) {
+  std::map<std::pair<int, std::vector<std::pair<int, int>>>, int> index;
+  std::vector<DxGroup> out;
+  for (int s = 0; s < geo->nshot; ++s) {
+    std::vector<std::pair<int, int>> rec;
+    for (int i = geo->rec_ptr[s]; i < geo->rec_ptr[s + 1]; ++i) rec.push_back({geo->rec_iz[i], geo->rec_ix[i]});
+    if (rec.empty()) continue;  // no receivers: no contribution
+    std::sort(rec.begin(), rec.end());
+    auto key = std::make_pair(shot_nt(g, geo, s), rec);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      DxGroup gr;
+      gr.nt = key.first;
+      for (auto& r : rec) {
+        gr.riz.push_back(r.first);
+        gr.rix.push_back(r.second);
+      }
+      it = index.emplace(key, (int)out.size()).first;
+      out.push_back(std::move(gr));
+    }
+    out[it->second].shots.push_back(s);
+  }
+  return out;
+}
+
+// geometry of one side of a group: sources at the receivers (impulse
+// responses) or the group's shots, no receivers
+struct DxGeo {
+  std::vector<int32_t> siz, six, ptr, nt;
+  fwi_geometry g{};
+  void finish() {
+    ptr.assign(siz.size() + 1, 0);
+    g.nshot = (int32_t)siz.size();
+    g.src_iz = siz.data();
+    g.src_ix = six.data();
+    g.rec_ptr = ptr.data();
+    g.rec_iz = ptr.data();
+    g.rec_ix = ptr.data();
+    g.nt = nt.data();
+  }
+};
+
+DxGeo dx_side(const fwi_geometry* geo, const DxGroup& gr, bool receivers) {
+  DxGeo o;
+  if (receivers) {
+    o.siz = gr.riz;
+    o.six = gr.rix;
+  } else {
+    for (int s : gr.shots) {
+      o.siz.push_back(geo->src_iz[s]);
+      o.six.push_back(geo->src_ix[s]);
+    }
+  }
+  o.nt.assign(o.siz.size(), gr.nt);
+  o.finish();
+  return o;
+}
+
+ExecChoice dx_choice(const fwi_grid* g, const fwi_exec* ex, int S) {
+  const int Z = g->nz + 2 * g->nsponge;
+  const int TZ = (ex && ex->tile_rows > 0) ? ex->tile_rows : default_tile_rows(Z);
+  const int pf = (ex && ex->prefetch > 0) ? ex->prefetch : 1;
+  // direct launches: the capture pointer is not baked into any graph
+  return ExecChoice{S, TZ, 0, pf, 1, S, TZ, 1, 1};
+}
+
+int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int hmax, double fmax,
+              DxLayout& o) {
+  if (int rc = check_inputs(g, geo)) return rc;
+  if (int rc = check_exec(ex)) return rc;
+  if (g->free_surface) return fail(FWI_ERR_ARG, "the exact offset diagonal needs the absorbing top");
+  if (hmax < 0 || hmax > 32 || hmax >= g->nx) return fail(FWI_ERR_ARG, "hmax must be in [0, 32] and < nx");
+  if (!(fmax >= 0) || !std::isfinite(fmax)) return fail(FWI_ERR_ARG, "fmax must be finite and >= 0");
+  const int64_t model = (int64_t)g->nz * g->nx;
+  const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : 8;
+  o = DxLayout{};
+  int Smax = 1, nshot_max = 1;
+  for (const DxGroup& gr : dx_groups(g, geo)) {
+    int L, K, nyq;
+    dx_bins(gr.nt, g->dt, fmax, L, K, nyq);
+    o.Tn = std::max(o.Tn, gr.nt - 1);
+    o.K = std::max(o.K, K);
+    nshot_max = std::max(nshot_max, (int)gr.shots.size());
+    for (int side = 0; side < 2; ++side) {
+      DxGeo dg = dx_side(geo, gr, side == 0);
+      const int S = std::min(Sreq, std::max(dg.g.nshot, 1));
+      Smax = std::max(Smax, S);
+      auto p = build_plan(g, &dg.g, dx_choice(g, ex, S), 0, FWI_WS_FORWARD, 0);
+      o.plan = std::max(o.plan, (size_t)p->L.total);
+    }
+  }
+  o.S = Smax;
+  size_t off = align_up(o.plan);
+  auto take = [&](size_t& field, size_t bytes) {
+    field = off;
+    off = align_up(off + bytes);
+  };
+  take(o.cap, sizeof(float) * (size_t)Smax * o.Tn * model);
+  take(o.C, sizeof(float) * (size_t)Smax * 2 * o.K * model);
+  take(o.PA, sizeof(float) * (size_t)o.K * model);
+  take(o.PB, sizeof(float) * (size_t)o.K * model);
+  take(o.W, sizeof(float) * (size_t)o.Tn * 2 * o.K);
+  take(o.imp, sizeof(float) * (size_t)g->nt_max);
+  take(o.wav, sizeof(float) * (size_t)nshot_max * g->nt_max);
+  o.total = off;
+  return FWI_OK;
+}
+
+std::mutex g_blas_mutex;
+std::map<int, rocblas_handle> g_blas;
+
+int blas_handle(hipStream_t s, rocblas_handle* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_blas_mutex);
+  auto it = g_blas.find(dev);
+  if (it == g_blas.end()) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_create_handle failed");
+    it = g_blas.emplace(dev, h).first;
+  }
+  if (rocblas_set_stream(it->second, s) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_set_stream failed");
+  *out = it->second;
+  return FWI_OK;
+}
+
 }  // namespace
 }  // namespace fwi
 
@@ -1491,6 +1649,97 @@ int fwi_hessian_diag(const fwi_grid* grid, const fwi_geometry* geom, const fwi_e
   for (int b = 0; b < p->nbatch; ++b) {
     if ((rc = forward_batch(*p, workspace, b, kFwdIllum, wavelet, wavelet_stride, s))) return rc;
     if ((rc = epilogue_batch(*p, workspace, b, false, v, H1, D, hmax, rcv_model, s))) return rc;
+  }
+  return FWI_OK;
+}
+
+size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec,
+                                             int hmax, double fmax) {
+  DxLayout o;
+  if (dx_layout(grid, geom, exec, hmax, fmax, o)) return 0;
+  return o.total;
+}
+
+int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                          const float* wavelet, int64_t wavelet_stride, int hmax, double fmax, float* diag,
+                          void* workspace, size_t ws_bytes, void* hip_stream) {
+  int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
+  if (rc) return rc;
+  if (!diag) return fail(FWI_ERR_ARG, "diag must not be NULL");
+  DxLayout o;
+  if ((rc = dx_layout(grid, geom, exec, hmax, fmax, o))) return rc;
+  if (ws_bytes < o.total)
+    return fail(FWI_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                       std::to_string(o.total));
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nz = grid->nz, nx = grid->nx;
+  const int64_t model = (int64_t)nz * nx;
+  HIP_TRY(launch_fill(diag, sizeof(float) * model * (2 * hmax + 1), s));
+  const std::vector<DxGroup> groups = dx_groups(grid, geom);
+  if (groups.empty()) return FWI_OK;
+  rocblas_handle blas = nullptr;
+  if ((rc = blas_handle(s, &blas))) return rc;
+  float* cap = at<float>(workspace, o.cap);
+  float* C = at<float>(workspace, o.C);
+  float* PA = at<float>(workspace, o.PA);
+  float* PB = at<float>(workspace, o.PB);
+  float* W = at<float>(workspace, o.W);
+  float* imp = at<float>(workspace, o.imp);
+  float* wav = at<float>(workspace, o.wav);
+  // the impulse [1, 0, 0, ...] that starts a receiver's response
+  HIP_TRY(launch_fill(imp, sizeof(float) * grid->nt_max, s));
+  HIP_TRY(launch_set((int32_t*)imp, 0x3f800000, s));
+  const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : 8;
+  const float one = 1.0f, zero = 0.0f;
+  for (const DxGroup& gr : groups) {
+    const int Tn = gr.nt - 1;
+    int L, K, nyq;
+    dx_bins(gr.nt, grid->dt, fmax, L, K, nyq);
+    HIP_TRY(launch_twiddle(W, Tn, K, L, s));
+    HIP_TRY(launch_fill(PA, sizeof(float) * (size_t)K * model, s));
+    HIP_TRY(launch_fill(PB, sizeof(float) * (size_t)K * model, s));
+    // the group's shots' wavelets, gathered in group order
+    const float* wsrc = wavelet;
+    int64_t wst = 0;
+    if (wavelet_stride != 0) {
+      for (size_t i = 0; i < gr.shots.size(); ++i)
+        HIP_TRY(hipMemcpyAsync(wav + i * (size_t)grid->nt_max, wavelet + (int64_t)gr.shots[i] * wavelet_stride,
+                               sizeof(float) * gr.nt, hipMemcpyDeviceToDevice, s));
+      wsrc = wav;
+      wst = grid->nt_max;
+    }
+    const int32_t* err = nullptr;  // the last plan's error flag (set if v fails its check)
+    for (int side = 0; side < 2; ++side) {
+      const bool rcv = side == 0;
+      DxGeo dg = dx_side(geom, gr, rcv);
+      const int S = std::min(Sreq, std::max(dg.g.nshot, 1));
+      auto p = build_plan(grid, &dg.g, dx_choice(grid, exec, S), 0, FWI_WS_FORWARD, 0);
+      if (p->L.total > o.plan) return fail(FWI_ERR_STATE, "exact offset diagonal: plan outgrew its region");
+      p->cap = cap;
+      p->cap_stride = (int64_t)Tn * model;
+      if ((rc = begin_call(*p, workspace, v, s))) return rc;
+      err = &at<Header>(workspace, p->L.hdr)->err;
+      for (int b = 0; b < p->nbatch; ++b) {
+        int nact = 0;
+        for (int i = 0; i < p->S; ++i) nact += p->slots[(size_t)b * p->S + i].shot >= 0;
+        if (rcv) rc = forward_batch(*p, workspace, b, kFwdCapU, imp, 0, s);
+        else rc = forward_batch(*p, workspace, b, kFwdCapD, wsrc, wst, s);
+        if (rc) return rc;
+        // spectra of the captured series: C[slot] = X[slot] (model x Tn) . W (Tn x 2K)
+        const rocblas_status bs = rocblas_sgemm_strided_batched(
+            blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)model, 2 * K, Tn, &one, cap,
+            (rocblas_int)model, (rocblas_stride)Tn * model, W, Tn, 0, &zero, C, (rocblas_int)model,
+            (rocblas_stride)2 * K * model, nact);
+        if (bs != rocblas_status_success)
+          return fail(FWI_ERR_HIP, std::string("rocblas_sgemm_strided_batched: ") + rocblas_status_to_string(bs));
+        HIP_TRY(launch_power_acc(C, model, K, nact, rcv ? PB : PA, s));
+      }
+    }
+    // (4 / v^6) h^4 / (dt^4 L): the source series is D / dt^2, the receiver
+    // series h^2 u (the impulse enters as 1 / h^2)
+    const double h2 = grid->dx * grid->dx, dt2 = grid->dt * grid->dt;
+    const float scale = (float)(4.0 * h2 * h2 / (dt2 * dt2 * L));
+    HIP_TRY(launch_diag_products(PA, PB, K, nyq, nz, nx, hmax, v, scale, diag, err, s));
   }
   return FWI_OK;
 }

@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from paper_1406_1864_amd import binding as B
-from paper_1406_1864_amd.synthetic import Grid, Geometry, tiny_24x16, layered_1024x384, ragged_1024x384
+from paper_1406_1864_amd.synthetic import (Grid, Geometry, tiny_24x16, layered_1024x384, offset_2048x768,
+                                           ragged_1024x384)
 
 
 @pytest.fixture(scope="module")
@@ -196,3 +197,39 @@ def test_reverse_launch_settings(lib):
     a = B.fwi_workspace_bytes(g, geo, B.make_exec(shots_in_flight=2, shots_in_flight_reverse=1), B.WS_GRADIENT)
     b = B.fwi_workspace_bytes(g, geo, B.make_exec(shots_in_flight=2), B.WS_GRADIENT)
     assert 0 < a < b                      # adjoint fields for one reverse slot instead of two
+
+
+def test_offset_diag_exact_sizing_and_rejects(lib):
+    """The exact offset diagonal's workspace grows with the band and the runs
+    in flight; bad offsets, a negative band, a free surface, a missing output
+    and a short workspace are rejected before any HIP call."""
+    g, geo = _tiny()
+    full = B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0)
+    band = B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 40.0)
+    one = B.fwi_offset_diag_exact_workspace_bytes(g, geo, B.make_exec(shots_in_flight=1), 4, 0.0)
+    assert 0 < band < full and 0 < one < full
+    for hmax, fmax in ((33, 0.0), (-1, 0.0), (24, 0.0), (4, -1.0), (4, float("nan"))):
+        assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, hmax, fmax) == 0, (hmax, fmax)
+    fake = 0x1000
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, None, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 40, 0.0, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, fake, fake, full - 1, stream=0)
+    assert e.value.code == B.FWI_ERR_WORKSPACE
+    g.free_surface = True
+    assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0) == 0
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
+
+
+def test_offset_diag_exact_fits_an_mi355x_at_full_size(lib):
+    """2048x768, nt 8000, band to 60 Hz, one run in flight: the captured
+    series and their spectra fit in 288 GB."""
+    w = offset_2048x768()
+    n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, B.make_exec(shots_in_flight=1), 16, 60.0)
+    assert 0 < n < 100e9, n
