@@ -195,12 +195,13 @@ def time_gn_hvp(args, grid, geom, w, d_obs, ex, dev):
 FP32_MFMA_PEAK_TFS = 157.3
 
 
-def time_offset_diag_exact(args, grid, geom, w, dev):
+def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     """fwi_offset_diag_exact on a subset: the first shots and an evenly spread
-    subset of their receivers (one group), band up to 4 f_peak, |h| <= 16.
-    Each run (a receiver's impulse response or a shot) is a forward sweep that
-    captures the model cells' series, then one FP32 GEMM with the DFT matrix;
-    the call's time is split into the two from the per-run costs below."""
+    subset of their receivers (one group), band up to 4 f_peak, |h| <= 16,
+    8 runs in flight, with each DFT arithmetic.  Each run (a receiver's
+    impulse response or a shot) is a forward sweep that captures the model
+    cells' series 1024 updates at a time, each chunk folded into the run's
+    spectra by a GEMM with the DFT matrix."""
     import torch
     from paper_1406_1864_amd import binding as B
     from paper_1406_1864_amd.synthetic import Geometry
@@ -211,35 +212,44 @@ def time_offset_diag_exact(args, grid, geom, w, dev):
                    (np.arange(ns + 1) * len(keep)).astype(np.int32),
                    np.tile(geom.rec_iz[keep], ns), np.tile(geom.rec_ix[keep], ns), geom.nt[:ns].copy())
     hmax, fmax = 16, 4.0 * w.f_peak
-    ex = B.make_exec(shots_in_flight=int(os.environ.get("FWI_EXACT_SIF", "1")))
-    nbytes = B.fwi_offset_diag_exact_workspace_bytes(grid, sub, ex, hmax, fmax)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    fn = lambda: B.offset_diag_exact(w.v_start, w.wavelet, grid, sub, hmax, fmax, ex, ws=ws, device=dev)
-    D = fn()
-    torch.cuda.synchronize()
-    assert bool(torch.isfinite(D).all())
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fn()
-    torch.cuda.synchronize()
-    call = (time.perf_counter() - t0) / args.steps
+    ex = B.make_exec(shots_in_flight=8)
     runs = ns + len(keep)
     nt = int(sub.nt[0])
     L = 2 * nt
     K = min(L // 2 + 1, int(np.floor(fmax * L * grid.dt + 1e-9)) + 1)
     model = grid.nz * grid.nx
     Z, X = grid.padded
-    gemm_flop = 2.0 * model * (nt - 1) * 2 * K          # per run
-    full_runs = w.geom.nshot + (b - a)
-    return {"value": runs / call, "unit": "runs/s (forward sweep with series capture + DFT GEMM)",
-            "shots": ns, "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K,
-            "nt": nt, "ms_per_call": 1e3 * call, "ms_per_run": 1e3 * call / runs,
-            "gemm_tflop_per_run": gemm_flop / 1e12,
-            "gemm_shape_per_run": [model, 2 * K, nt - 1],
-            "cell_updates_per_run": float(Z * X * (nt - 1)),
-            "workspace_gb": nbytes / 1e9,
-            "full_problem_s_extrapolated": full_runs * call / runs,
-            "full_problem_runs": full_runs}
+    gemm_flop = 2.0 * model * (nt - 1) * 2 * K          # per run, FP32-equivalent
+    full_runs = full_shots + (b - a)
+    out = {"unit": "runs/s (forward sweep with series capture + DFT GEMM)", "shots": ns,
+           "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": 8,
+           "gemm_shape_per_run": [model, 2 * K, nt - 1], "gemm_tflop_per_run": gemm_flop / 1e12,
+           "cell_updates_per_run": float(Z * X * (nt - 1)), "full_problem_runs": full_runs}
+    Dref = None
+    for name, dft in (("fp32", B.DFT_FP32), ("bf16x3", B.DFT_BF16X3)):
+        nbytes = B.fwi_offset_diag_exact_workspace_bytes(grid, sub, ex, hmax, fmax, dft)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        fn = lambda: B.offset_diag_exact(w.v_start, w.wavelet, grid, sub, hmax, fmax, ex, ws=ws, device=dev,
+                                         dft=dft)
+        D = fn()
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(D).all())
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        call = (time.perf_counter() - t0) / args.steps
+        r = {"value": runs / call, "ms_per_call": 1e3 * call, "ms_per_run": 1e3 * call / runs,
+             "workspace_gb": nbytes / 1e9, "full_problem_s_extrapolated": full_runs * call / runs}
+        if Dref is None:
+            Dref = D.double()
+        else:
+            r["rel_l2_vs_fp32"] = float(torch.linalg.norm(D.double() - Dref) / torch.linalg.norm(Dref))
+        out[name] = r
+        del ws, D
+        torch.cuda.empty_cache()
+    out["value"] = out["bf16x3"]["value"]
+    return out
 
 
 def main():
@@ -436,7 +446,7 @@ def main():
     if args.gn:
         out["gn_hvp"] = time_gn_hvp(args, grid, geom, w, d_obs, ex, dev)
     if args.exact_diag > 0:
-        out["offset_diag_exact"] = time_offset_diag_exact(args, grid, geom, w, dev)
+        out["offset_diag_exact"] = time_offset_diag_exact(args, grid, geom, w, dev, full_shots)
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded

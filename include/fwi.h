@@ -323,17 +323,24 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  * Hz); fmax = 0 keeps all nt + 1 of them.  With every bin this is the norm of
  * the extended-Born column of (x, h) over the whole response (conventional
  * misfit).  Horizontal offsets |h| <= hmax <= 32; terms with x+h or x-h
- * outside the model are 0.  Shots are grouped by (record length, receiver
- * set); each group costs one forward run per receiver and per shot, and the
- * workspace holds the model cells' series of shots_in_flight runs (default 8)
- * and their spectra: see fwi_offset_diag_exact_workspace_bytes.  Not with a
- * free surface.  diag: device [2 hmax + 1][nz][nx], overwritten.  The DFT is
- * a GEMM through rocBLAS (FP32). */
+ * outside the model are 0.
+ *
+ * Shots are grouped by (record length, receiver set); each group costs one
+ * forward run per receiver and per shot, shots_in_flight runs at a time
+ * (default 8).  A run's series are captured 1024 updates at a time and folded
+ * into its spectra by a GEMM with the DFT matrix (rocBLAS), in FP32 (dft =
+ * FWI_DFT_FP32) or as three bf16 products with FP32 accumulation of the
+ * series and the DFT matrix split into bf16 pairs (FWI_DFT_BF16X3: about 16
+ * significant bits per product, the lo*lo term dropped).  The workspace holds
+ * the chunks and spectra of the runs in flight: see
+ * fwi_offset_diag_exact_workspace_bytes (0 on bad arguments).  Not with a
+ * free surface.  diag: device [2 hmax + 1][nz][nx], overwritten. */
+enum { FWI_DFT_FP32 = 0, FWI_DFT_BF16X3 = 1 };
 size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
-                                             const fwi_exec *exec, int hmax, double fmax);
+                                             const fwi_exec *exec, int hmax, double fmax, int dft);
 int fwi_offset_diag_exact(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
                           const float *v, const float *wavelet, int64_t wavelet_stride,
-                          int hmax, double fmax, float *diag,
+                          int hmax, double fmax, int dft, float *diag,
                           void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Preconditioned gradient (section 3.1): out = grad / (P + eps * max P) with

@@ -39,6 +39,7 @@ MISFIT_L2, MISFIT_TIME_INTEGRAL = 0, 1
 HESS_EQ1, HESS_OFFSET = 0, 1
 RCV_PM, RCV_NONE = 0, 1
 PRECOND_SHOT, PRECOND_OFFSET = 0, 1
+DFT_FP32, DFT_BF16X3 = 0, 1
 WS_FORWARD, WS_GRADIENT, WS_HESSIAN, WS_AUTOGRAD, WS_PRECOND, WS_EXTIMAGE, WS_BORN, WS_GNHVP = range(8)
 
 MISFIT_EQ3_LITERAL = 2
@@ -101,10 +102,10 @@ _SIGS = {
                                     c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
     "fwi_offset_diag_exact_workspace_bytes": (c_size_t, [POINTER(fwi_grid), POINTER(fwi_geometry),
-                                                         POINTER(fwi_exec), c_int, ctypes.c_double]),
+                                                         POINTER(fwi_exec), c_int, ctypes.c_double, c_int]),
     "fwi_offset_diag_exact": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
-                                      c_void_p, c_int64, c_int, ctypes.c_double, c_void_p, c_void_p, c_size_t,
-                                      c_void_p]),
+                                      c_void_p, c_int64, c_int, ctypes.c_double, c_int, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]),
     "fwi_precondition": (c_int, [POINTER(fwi_grid), c_void_p, c_void_p, c_int, c_void_p, c_int, c_float,
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
     "fwi_status": (c_int, [c_void_p, c_void_p]),
@@ -290,18 +291,19 @@ def fwi_misfit_backward(grid, geom, exec_, v, wavelet, wavelet_stride, grad_scal
                                              _ptr(workspace), int(ws_bytes), _stream(stream)))
 
 
-def fwi_offset_diag_exact_workspace_bytes(grid, geom, exec_, hmax, fmax) -> int:
+def fwi_offset_diag_exact_workspace_bytes(grid, geom, exec_, hmax, fmax, dft=DFT_FP32) -> int:
     g, G = make_grid(grid), _geo(geom)
     return int(load().fwi_offset_diag_exact_workspace_bytes(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_),
-                                                            int(hmax), float(fmax)))
+                                                            int(hmax), float(fmax), int(dft)))
 
 
-def fwi_offset_diag_exact(grid, geom, exec_, v, wavelet, wavelet_stride, hmax, fmax, diag, workspace, ws_bytes,
-                          stream=None):
+def fwi_offset_diag_exact(grid, geom, exec_, v, wavelet, wavelet_stride, hmax, fmax, dft, diag, workspace,
+                          ws_bytes, stream=None):
     g, G = make_grid(grid), _geo(geom)
     return _check(load().fwi_offset_diag_exact(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v),
                                                _ptr(wavelet), int(wavelet_stride), int(hmax), float(fmax),
-                                               _ptr(diag), _ptr(workspace), int(ws_bytes), _stream(stream)))
+                                               int(dft), _ptr(diag), _ptr(workspace), int(ws_bytes),
+                                               _stream(stream)))
 
 
 def fwi_precondition(grid, v, grad, kind, hdiag, hmax, eps, out, workspace, ws_bytes, stream=None):
@@ -453,20 +455,22 @@ def hessian_diag(v, wavelet, grid, geom, kind=HESS_EQ1, hmax=0, rcv_model="pm", 
     return out
 
 
-def offset_diag_exact(v, wavelet, grid, geom, hmax, fmax=0.0, exec_=None, ws=None, device="cuda"):
+def offset_diag_exact(v, wavelet, grid, geom, hmax, fmax=0.0, exec_=None, ws=None, device="cuda", dft=None):
     """Offset diagonal with the exact receiver term, D[2 hmax + 1][nz][nx]
-    (fmax in Hz bounds the frequency band, 0 keeps every bin)."""
+    (fmax in Hz bounds the frequency band, 0 keeps every bin; dft selects
+    the DFT GEMM's arithmetic, DFT_BF16X3 by default)."""
+    dft = DFT_BF16X3 if dft is None else dft
     torch = _torch()
     G = _geo(geom)
     vd = _dev(v, torch.float32, device)
     w, ws_ = _wavelet(wavelet, grid.nt_max, device)
     out = torch.empty((2 * hmax + 1, grid.nz, grid.nx), dtype=torch.float32, device=device)
     if ws is None:
-        n = fwi_offset_diag_exact_workspace_bytes(grid, G, exec_, hmax, fmax)
+        n = fwi_offset_diag_exact_workspace_bytes(grid, G, exec_, hmax, fmax, dft)
         if n == 0:
             raise FwiError(FWI_ERR_ARG, last_error())
         ws = torch.empty(n, dtype=torch.uint8, device=device)
-    fwi_offset_diag_exact(grid, G, exec_, vd, w, ws_, hmax, fmax, out, ws, ws.numel())
+    fwi_offset_diag_exact(grid, G, exec_, vd, w, ws_, hmax, fmax, dft, out, ws, ws.numel())
     return out
 
 

@@ -112,10 +112,15 @@ struct StepArgs {
   // Born modelling (forward sweep only): the perturbation wavefield
   float* bu;            // [cs][3][field]  du[n] at level n & 1, its increment at level 2
   const float* bw;      // 2 dv / v on the padded grid (zero outside the model)
-  // series capture (forward sweep, kFwdCapD / kFwdCapU): the model cells'
-  // value of update n goes to cap[slot * cap_stride + n * model + cell]
-  float* cap;
-  int64_t cap_stride;
+  // series capture (forward sweep, kFwdCapD / kFwdCapU).  The model cells
+  // are cut into blocks of 2^cap_lg; entry e = slot * cap_nblk + block holds
+  // cap_T columns of 2^cap_lg rows, and the value of update n of cell `cell`
+  // goes to element (e * cap_T + n - cap_n0) * 2^cap_lg + (cell & (2^cap_lg
+  // - 1)), as FP32, or (cap_split) as uint16 bf16 values hi, lo, hi at that
+  // element and cap_lo, 2 cap_lo elements further on
+  void* cap;
+  int64_t cap_lo;
+  int32_t cap_n0, cap_split, cap_T, cap_nblk, cap_lg;
 };
 
 // Extended imaging over one window of reverse launch steps
@@ -208,11 +213,16 @@ hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const fl
                                const double* scale, double fac, float* grad, const int32_t* err, hipStream_t s);
 hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
                              const int32_t* trace_shot, float* data, hipStream_t s);
-// exact offset diagonal: W[t + c Tn] = cos / sin (2 pi k t / L) for c = 2k / 2k+1,
-// t < Tn, k < K (the DFT matrix of the captured series)
-hipError_t launch_twiddle(float* W, int Tn, int K, int L, hipStream_t s);
-// P[k][cell] += sum over nslots of C[slot][2k][cell]^2 + C[slot][2k+1][cell]^2
-hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, float* P, hipStream_t s);
+// exact offset diagonal, the DFT matrix of the captured series:
+// w(t, c) = cos / sin (2 pi k t / L) for c = 2k / 2k+1, t < Tn, k < K.
+// Tc = 0: FP32 W[t + c ldw] (rows Tn .. ldw-1 zero).  Tc > 0: for each chunk
+// q of tc = min(Tc, Tn - q Tc) steps, the bf16 matrix [Wh; Wh; Wl] of the
+// chunk's rows (3 tc rows, ld 3 Tc) at element q 2K 3Tc
+hipError_t launch_twiddle(void* W, int Tn, int ldw, int K, int L, int Tc, hipStream_t s);
+// P[k][cell] += sum over nslots of C[e][2k][r]^2 + C[e][2k+1][r]^2 with
+// e = slot nblk + (cell >> lg), r = cell & (2^lg - 1) (ld 2^lg per column)
+hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, int nblk, int lg, float* P,
+                            hipStream_t s);
 // D[h][z][x] += scale / v^6 sum_k m_k PA[k][z][x+h] PB[k][z][x-h] for |h| <= hmax
 // (both columns in the model), m_0 = 1, m_{K-1} = 1 if nyq, else 2
 hipError_t launch_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,

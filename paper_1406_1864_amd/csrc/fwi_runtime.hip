@@ -153,8 +153,6 @@ struct Plan {
   int fwd_steps = 1;           // time steps per launch of the gradient's forward sweep (1 or 2)
   int ulevels = kULevels, llevels = kLamLevels;
   int XT2 = 0;                 // tiles of the two-step reverse sweep along x
-  float* cap = nullptr;        // series capture of the forward sweep (exact offset diagonal)
-  int64_t cap_stride = 0;
   double sp_a = 0.0;
   double dx = 0, dt = 0;
   std::vector<ShotDesc> shots;
@@ -525,8 +523,6 @@ StepArgs step_args(const Plan& p, void* ws, int batch, int phase, const float* w
   a.ext_T = p.ext_T;
   a.bu = p.born ? at<float>(ws, p.L.bu) + p.d.guard : nullptr;
   a.bw = p.born ? at<float>(ws, p.L.bw) : nullptr;
-  a.cap = p.cap;
-  a.cap_stride = p.cap_stride;
   return a;
 }
 
@@ -1183,7 +1179,31 @@ struct DxLayout {
   size_t plan = 0;        // plan region (offset 0)
   size_t cap = 0, C = 0, PA = 0, PB = 0, W = 0, imp = 0, wav = 0, total = 0;
   int Tn = 0, K = 0;      // largest series length and bin count
+  int Tc = 0;             // time steps captured between two GEMMs
+  int lg = 0, nblk = 0;   // GEMM row blocks of 2^lg model cells
 };
+
+// steps captured per chunk: the captured series of S runs take S Tc model
+// cells of 4 bytes (FP32, or a bf16 pair)
+constexpr int kDxChunk = 1024;
+
+// The GEMMs take blocks of at most 2^16 model cells as batch entries, so
+// that every operand offset inside one entry stays far below 2^31 elements
+// whatever the grid, chunk and band (the library indexes within a matrix in
+// 32 bits)
+constexpr int kDxBlockLog2 = 16;
+
+void dx_blocks(int64_t model, int& lg, int& nblk) {
+  lg = 0;
+  while (lg < kDxBlockLog2 && ((int64_t)1 << lg) < model) ++lg;
+  nblk = (int)((model + ((int64_t)1 << lg) - 1) >> lg);
+}
+
+// leading dimension of the DFT matrix: whole 256-byte lines per column, so
+// that the GEMM's loads of it stay aligned
+int dx_ldw(int Tn) { return (Tn + 63) / 64 * 64; }
+
+size_t dx_sample_bytes(int dft) { return dft == FWI_DFT_FP32 ? 4 : 6; }
 
 void dx_bins(int nt, double dt, double fmax, int& L, int& K, int& nyq) {
   L = 2 * nt;
@@ -1258,13 +1278,14 @@ ExecChoice dx_choice(const fwi_grid* g, const fwi_exec* ex, int S) {
   return ExecChoice{S, TZ, 0, pf, 1, S, TZ, 1, 1};
 }
 
-int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int hmax, double fmax,
+int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int hmax, double fmax, int dft,
               DxLayout& o) {
   if (int rc = check_inputs(g, geo)) return rc;
   if (int rc = check_exec(ex)) return rc;
   if (g->free_surface) return fail(FWI_ERR_ARG, "the exact offset diagonal needs the absorbing top");
   if (hmax < 0 || hmax > 32 || hmax >= g->nx) return fail(FWI_ERR_ARG, "hmax must be in [0, 32] and < nx");
   if (!(fmax >= 0) || !std::isfinite(fmax)) return fail(FWI_ERR_ARG, "fmax must be finite and >= 0");
+  if (dft != FWI_DFT_FP32 && dft != FWI_DFT_BF16X3) return fail(FWI_ERR_ARG, "dft must be FWI_DFT_FP32 or FWI_DFT_BF16X3");
   const int64_t model = (int64_t)g->nz * g->nx;
   const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : 8;
   o = DxLayout{};
@@ -1284,34 +1305,41 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
     }
   }
   o.S = Smax;
+  o.Tc = std::max(1, std::min(o.Tn, kDxChunk));
+  dx_blocks(model, o.lg, o.nblk);
+  const size_t rows = (size_t)o.nblk << o.lg;  // model cells padded to whole blocks
   size_t off = align_up(o.plan);
   auto take = [&](size_t& field, size_t bytes) {
     field = off;
     off = align_up(off + bytes);
   };
-  take(o.cap, sizeof(float) * (size_t)Smax * o.Tn * model);
-  take(o.C, sizeof(float) * (size_t)Smax * 2 * o.K * model);
+  // the chunk of 4 (FP32) or 6 (bf16 hi, lo, hi) bytes per sample
+  take(o.cap, dx_sample_bytes(dft) * (size_t)Smax * o.Tc * rows);
+  take(o.C, sizeof(float) * (size_t)Smax * 2 * o.K * rows);
   take(o.PA, sizeof(float) * (size_t)o.K * model);
   take(o.PB, sizeof(float) * (size_t)o.K * model);
-  take(o.W, sizeof(float) * (size_t)o.Tn * 2 * o.K);
+  const int nq = (o.Tn + o.Tc - 1) / o.Tc;
+  take(o.W, dft == FWI_DFT_FP32 ? sizeof(float) * (size_t)dx_ldw(o.Tn) * 2 * o.K
+                                : sizeof(uint16_t) * (size_t)nq * 2 * o.K * 3 * o.Tc);
   take(o.imp, sizeof(float) * (size_t)g->nt_max);
   take(o.wav, sizeof(float) * (size_t)nshot_max * g->nt_max);
   o.total = off;
   return FWI_OK;
 }
 
-std::mutex g_blas_mutex;
-std::map<int, rocblas_handle> g_blas;
+// Per device rocBLAS handles; g_dx_mutex is held while a call sets its
+// handle's stream and enqueues its work.
+std::mutex g_dx_mutex;
+std::map<int, rocblas_handle> g_dx_blas;
 
-int blas_handle(hipStream_t s, rocblas_handle* out) {
+int dx_blas(hipStream_t s, rocblas_handle* out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lock(g_blas_mutex);
-  auto it = g_blas.find(dev);
-  if (it == g_blas.end()) {
+  auto it = g_dx_blas.find(dev);
+  if (it == g_dx_blas.end()) {
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_create_handle failed");
-    it = g_blas.emplace(dev, h).first;
+    it = g_dx_blas.emplace(dev, h).first;
   }
   if (rocblas_set_stream(it->second, s) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_set_stream failed");
   *out = it->second;
@@ -1654,48 +1682,77 @@ int fwi_hessian_diag(const fwi_grid* grid, const fwi_geometry* geom, const fwi_e
 }
 
 size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec,
-                                             int hmax, double fmax) {
+                                             int hmax, double fmax, int dft) {
   DxLayout o;
-  if (dx_layout(grid, geom, exec, hmax, fmax, o)) return 0;
+  if (dx_layout(grid, geom, exec, hmax, fmax, dft, o)) return 0;
   return o.total;
 }
 
 int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
-                          const float* wavelet, int64_t wavelet_stride, int hmax, double fmax, float* diag,
+                          const float* wavelet, int64_t wavelet_stride, int hmax, double fmax, int dft, float* diag,
                           void* workspace, size_t ws_bytes, void* hip_stream) {
   int rc = common_checks(grid, geom, v, wavelet, wavelet_stride, workspace);
   if (rc) return rc;
   if (!diag) return fail(FWI_ERR_ARG, "diag must not be NULL");
   DxLayout o;
-  if ((rc = dx_layout(grid, geom, exec, hmax, fmax, o))) return rc;
+  if ((rc = dx_layout(grid, geom, exec, hmax, fmax, dft, o))) return rc;
   if (ws_bytes < o.total)
     return fail(FWI_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
                                        std::to_string(o.total));
   hipStream_t s = (hipStream_t)hip_stream;
   const int nz = grid->nz, nx = grid->nx;
   const int64_t model = (int64_t)nz * nx;
+  const bool split = dft == FWI_DFT_BF16X3;
   HIP_TRY(launch_fill(diag, sizeof(float) * model * (2 * hmax + 1), s));
   const std::vector<DxGroup> groups = dx_groups(grid, geom);
   if (groups.empty()) return FWI_OK;
+  std::lock_guard<std::mutex> lock(g_dx_mutex);
   rocblas_handle blas = nullptr;
-  if ((rc = blas_handle(s, &blas))) return rc;
-  float* cap = at<float>(workspace, o.cap);
+  if ((rc = dx_blas(s, &blas))) return rc;
+  void* cap = at<char>(workspace, o.cap);
   float* C = at<float>(workspace, o.C);
   float* PA = at<float>(workspace, o.PA);
   float* PB = at<float>(workspace, o.PB);
-  float* W = at<float>(workspace, o.W);
+  void* W = at<char>(workspace, o.W);
   float* imp = at<float>(workspace, o.imp);
   float* wav = at<float>(workspace, o.wav);
   // the impulse [1, 0, 0, ...] that starts a receiver's response
   HIP_TRY(launch_fill(imp, sizeof(float) * grid->nt_max, s));
   HIP_TRY(launch_set((int32_t*)imp, 0x3f800000, s));
   const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : 8;
-  const float one = 1.0f, zero = 0.0f;
+  // C[e] (+)= X[e] . Wq for chunk q (updates k0 .. k0+tc-1) and every entry
+  // e (slot, block of mb cells): FP32, X the chunk's series (mb x tc, ld mb)
+  // and Wq rows k0 .. of the DFT matrix (ld ldw); split, [Xh | Xl | Xh]
+  // (mb x 3tc) and the chunk's [Wh; Wh; Wl] (ld 3 Tc), one bf16 GEMM with
+  // FP32 accumulation.  C[e] is mb x 2K (ld mb).
+  const int mb = 1 << o.lg;
+  auto gemm = [&](int ldw, int K, int q, int k0, int tc, int nact) -> int {
+    const float one = 1.0f, beta0 = k0 > 0 ? 1.0f : 0.0f;
+    const int batch = nact * o.nblk;
+    const rocblas_stride sc = (rocblas_stride)2 * K * mb;
+    rocblas_status bs;
+    if (!split) {
+      bs = rocblas_sgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, mb, 2 * K, tc, &one,
+                                         (const float*)cap, mb, (rocblas_stride)o.Tc * mb, (const float*)W + k0,
+                                         ldw, 0, &beta0, C, mb, sc, batch);
+    } else {
+      const uint16_t* wq = (const uint16_t*)W + (int64_t)q * 2 * K * 3 * o.Tc;
+      bs = rocblas_gemm_strided_batched_ex(
+          blas, rocblas_operation_none, rocblas_operation_none, mb, 2 * K, 3 * tc, &one, cap, rocblas_datatype_bf16_r,
+          mb, (rocblas_stride)3 * o.Tc * mb, wq, rocblas_datatype_bf16_r, 3 * o.Tc, 0, &beta0, C,
+          rocblas_datatype_f32_r, mb, sc, C, rocblas_datatype_f32_r, mb, sc, batch, rocblas_datatype_f32_r,
+          rocblas_gemm_algo_standard, 0, 0);
+    }
+    if (bs != rocblas_status_success)
+      return fail(FWI_ERR_HIP, std::string("rocBLAS GEMM of the DFT: ") + rocblas_status_to_string(bs));
+    return FWI_OK;
+  };
   for (const DxGroup& gr : groups) {
     const int Tn = gr.nt - 1;
     int L, K, nyq;
     dx_bins(gr.nt, grid->dt, fmax, L, K, nyq);
-    HIP_TRY(launch_twiddle(W, Tn, K, L, s));
+    const int ldw = dx_ldw(Tn);
+    HIP_TRY(launch_twiddle(W, Tn, ldw, K, L, split ? o.Tc : 0, s));
     HIP_TRY(launch_fill(PA, sizeof(float) * (size_t)K * model, s));
     HIP_TRY(launch_fill(PB, sizeof(float) * (size_t)K * model, s));
     // the group's shots' wavelets, gathered in group order
@@ -1714,25 +1771,35 @@ int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const 
       DxGeo dg = dx_side(geom, gr, rcv);
       const int S = std::min(Sreq, std::max(dg.g.nshot, 1));
       auto p = build_plan(grid, &dg.g, dx_choice(grid, exec, S), 0, FWI_WS_FORWARD, 0);
-      if (p->L.total > o.plan) return fail(FWI_ERR_STATE, "exact offset diagonal: plan outgrew its region");
-      p->cap = cap;
-      p->cap_stride = (int64_t)Tn * model;
+      if (p->L.total > o.plan || p->S > o.S) return fail(FWI_ERR_STATE, "exact offset diagonal: plan outgrew its region");
       if ((rc = begin_call(*p, workspace, v, s))) return rc;
       err = &at<Header>(workspace, p->L.hdr)->err;
+      const int flags = rcv ? kFwdCapU : kFwdCapD;
       for (int b = 0; b < p->nbatch; ++b) {
         int nact = 0;
         for (int i = 0; i < p->S; ++i) nact += p->slots[(size_t)b * p->S + i].shot >= 0;
-        if (rcv) rc = forward_batch(*p, workspace, b, kFwdCapU, imp, 0, s);
-        else rc = forward_batch(*p, workspace, b, kFwdCapD, wsrc, wst, s);
-        if (rc) return rc;
-        // spectra of the captured series: C[slot] = X[slot] (model x Tn) . W (Tn x 2K)
-        const rocblas_status bs = rocblas_sgemm_strided_batched(
-            blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)model, 2 * K, Tn, &one, cap,
-            (rocblas_int)model, (rocblas_stride)Tn * model, W, Tn, 0, &zero, C, (rocblas_int)model,
-            (rocblas_stride)2 * K * model, nact);
-        if (bs != rocblas_status_success)
-          return fail(FWI_ERR_HIP, std::string("rocblas_sgemm_strided_batched: ") + rocblas_status_to_string(bs));
-        HIP_TRY(launch_power_acc(C, model, K, nact, rcv ? PB : PA, s));
+        const SlotInfo* slots = at<SlotInfo>(workspace, p->L.slots) + (size_t)b * p->S;
+        HIP_TRY(launch_fill_slots(at<float>(workspace, p->L.u), p->ulevels * p->d.field,
+                                  p->ulevels * p->d.field + p->d.guard, slots, p->S, 1, s));
+        StepArgs a = step_args(*p, workspace, b, kPhaseFwd, rcv ? imp : wsrc, rcv ? 0 : wst, false);
+        a.cap_T = (split ? 3 : 1) * o.Tc;  // columns per entry
+        a.cap_nblk = o.nblk;
+        a.cap_lg = o.lg;
+        a.cap_split = split;
+        // the series in chunks of Tc updates, each folded into the spectra
+        // (on one stream: forward sweeps run beside a GEMM slowed both)
+        a.cap = cap;
+        for (int k0 = 0, c = 0; k0 < Tn; k0 += o.Tc, ++c) {
+          const int tc = std::min(o.Tc, Tn - k0);
+          a.cap_n0 = k0;
+          a.cap_lo = (int64_t)tc * mb;  // the chunk's three column blocks
+          for (int k = k0; k < k0 + tc; ++k) {
+            a.step = k;
+            HIP_TRY(launch_forward(a, flags, p->pf_fwd, s));
+          }
+          if ((rc = gemm(ldw, K, c, k0, tc, nact))) return rc;
+        }
+        HIP_TRY(launch_power_acc(C, model, K, nact, o.nblk, o.lg, rcv ? PB : PA, s));
       }
     }
     // (4 / v^6) h^4 / (dt^4 L): the source series is D / dt^2, the receiver

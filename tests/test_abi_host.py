@@ -208,28 +208,34 @@ def test_offset_diag_exact_sizing_and_rejects(lib):
     band = B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 40.0)
     one = B.fwi_offset_diag_exact_workspace_bytes(g, geo, B.make_exec(shots_in_flight=1), 4, 0.0)
     assert 0 < band < full and 0 < one < full
-    for hmax, fmax in ((33, 0.0), (-1, 0.0), (24, 0.0), (4, -1.0), (4, float("nan"))):
-        assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, hmax, fmax) == 0, (hmax, fmax)
+    assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0, B.DFT_BF16X3) > full   # 6 B per sample
+    for hmax, fmax, dft in ((33, 0.0, 0), (-1, 0.0, 0), (24, 0.0, 0), (4, -1.0, 0), (4, float("nan"), 0),
+                            (4, 0.0, 2)):
+        assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, hmax, fmax, dft) == 0, (hmax, fmax, dft)
     fake = 0x1000
     with pytest.raises(B.FwiError) as e:
-        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, None, fake, 1 << 40, stream=0)
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, 0, None, fake, 1 << 40, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
     with pytest.raises(B.FwiError) as e:
-        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 40, 0.0, fake, fake, 1 << 40, stream=0)
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 40, 0.0, 0, fake, fake, 1 << 40, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
     with pytest.raises(B.FwiError) as e:
-        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, fake, fake, full - 1, stream=0)
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, 0, fake, fake, full - 1, stream=0)
     assert e.value.code == B.FWI_ERR_WORKSPACE
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, 3, fake, fake, 1 << 40, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
     g.free_surface = True
     assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0) == 0
     with pytest.raises(B.FwiError) as e:
-        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, fake, fake, 1 << 40, stream=0)
+        B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, 0, fake, fake, 1 << 40, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
 
 
 def test_offset_diag_exact_fits_an_mi355x_at_full_size(lib):
-    """2048x768, nt 8000, band to 60 Hz, one run in flight: the captured
-    series and their spectra fit in 288 GB."""
+    """2048x768, nt 8000, band to 60 Hz, 8 runs in flight: the captured
+    chunks and the spectra fit in 288 GB."""
     w = offset_2048x768()
-    n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, B.make_exec(shots_in_flight=1), 16, 60.0)
-    assert 0 < n < 100e9, n
+    for dft in (B.DFT_FP32, B.DFT_BF16X3):
+        n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, B.make_exec(shots_in_flight=8), 16, 60.0, dft)
+        assert 0 < n < 150e9, (dft, n)

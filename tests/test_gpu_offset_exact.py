@@ -39,9 +39,13 @@ def check(tag, ref, got, hmax):
         assert np.all(got[hmax - h][:, :h] == 0) and np.all(got[hmax - h][:, nx - h:] == 0)
 
 
+DFTS = {"fp32": B.DFT_FP32, "bf16x3": B.DFT_BF16X3}
+
+
+@pytest.mark.parametrize("dft", list(DFTS))
 @pytest.mark.parametrize("fmax", [0.0, 40.0])
 @pytest.mark.parametrize("sif", [0, 1])
-def test_offset_diag_exact_tiny(fmax, sif):
+def test_offset_diag_exact_tiny(fmax, sif, dft):
     """Two shots sharing one receiver set (one group); every bin or the band
     up to four times the Ricker peak; the default number of runs in flight or
     one run per batch."""
@@ -49,8 +53,8 @@ def test_offset_diag_exact_tiny(fmax, sif):
     hmax = 4
     ref = oracle.offset_diag_spectral(w.v_start, w.grid, w.geom, w.wavelet, hmax, fmax=fmax or None)
     ex = B.make_exec(shots_in_flight=sif) if sif else None
-    got = B.offset_diag_exact(w.v_start, w.wavelet, w.grid, w.geom, hmax, fmax, ex)
-    check(f"tiny fmax={fmax} sif={sif}", ref, got, hmax)
+    got = B.offset_diag_exact(w.v_start, w.wavelet, w.grid, w.geom, hmax, fmax, ex, dft=DFTS[dft])
+    check(f"tiny fmax={fmax} sif={sif} {dft}", ref, got, hmax)
 
 
 def ragged_with_short_record():
@@ -70,15 +74,16 @@ def ragged_with_short_record():
     return grid, geom, v_start, wav
 
 
+@pytest.mark.parametrize("dft", list(DFTS))
 @pytest.mark.parametrize("sif", [2, 8])
-def test_offset_diag_exact_ragged(sif):
+def test_offset_diag_exact_ragged(sif, dft):
     """Every shot its own group (receiver sets and record lengths differ),
     per-shot wavelets, receivers in a well, on the model's edges and corners."""
     grid, geom, v, wav = ragged_with_short_record()
     hmax = 8
     ref = oracle.offset_diag_spectral(v, grid, geom, wav, hmax)
-    got = B.offset_diag_exact(v, wav, grid, geom, hmax, 0.0, B.make_exec(shots_in_flight=sif))
-    check(f"ragged sif={sif}", ref, got, hmax)
+    got = B.offset_diag_exact(v, wav, grid, geom, hmax, 0.0, B.make_exec(shots_in_flight=sif), dft=DFTS[dft])
+    check(f"ragged sif={sif} {dft}", ref, got, hmax)
 
 
 def test_offset_diag_exact_skips_shots_without_receivers():
@@ -90,7 +95,8 @@ def test_offset_diag_exact_skips_shots_without_receivers():
     check("ragged, one shot without receivers", ref, got, hmax)
 
 
-def test_offset_diag_exact_anomaly_receiver_subset():
+@pytest.mark.parametrize("dft", list(DFTS))
+def test_offset_diag_exact_anomaly_receiver_subset(dft):
     """The 200x100 anomaly model and shot (nt 1000, Ricker 10 Hz, band to
     40 Hz, offsets up to 16 cells) with 6 of its 100 receivers, so that the
     oracle's impulse responses stay within seconds."""
@@ -100,8 +106,8 @@ def test_offset_diag_exact_anomaly_receiver_subset():
     geom = Geometry(g.src_iz, g.src_ix, np.array([0, len(keep)], np.int32), g.rec_iz[keep], g.rec_ix[keep], g.nt)
     hmax = 16
     ref = oracle.offset_diag_spectral(w.v_start, w.grid, geom, w.wavelet, hmax, fmax=40.0)
-    got = B.offset_diag_exact(w.v_start, w.wavelet, w.grid, geom, hmax, 40.0)
-    check("anomaly 200x100, 6 receivers", ref, got, hmax)
+    got = B.offset_diag_exact(w.v_start, w.wavelet, w.grid, geom, hmax, 40.0, dft=DFTS[dft])
+    check(f"anomaly 200x100, 6 receivers, {dft}", ref, got, hmax)
 
 
 def test_offset_diag_exact_repeated_calls_agree():
@@ -109,7 +115,7 @@ def test_offset_diag_exact_repeated_calls_agree():
     zero on every call with the same workspace."""
     grid, geom, v, wav = ragged_with_short_record()
     ex = B.make_exec(shots_in_flight=2)
-    n = B.fwi_offset_diag_exact_workspace_bytes(grid, geom, ex, 5, 0.0)
+    n = B.fwi_offset_diag_exact_workspace_bytes(grid, geom, ex, 5, 0.0, B.DFT_BF16X3)
     ws = torch.empty(n, dtype=torch.uint8, device="cuda")
     a = B.offset_diag_exact(v, wav, grid, geom, 5, 0.0, ex, ws=ws)
     b = B.offset_diag_exact(v, wav, grid, geom, 5, 0.0, ex, ws=ws)
@@ -126,7 +132,8 @@ def band_power(x, L, K):
     return m, X.real ** 2 + X.imag ** 2
 
 
-def test_offset_diag_exact_full_size_reciprocity():
+@pytest.mark.parametrize("dft", list(DFTS))
+def test_offset_diag_exact_full_size_reciprocity(dft):
     """2048x768 at dx = 6.25 m (64-cell sponge, nt 8000, dt 0.5 ms, Ricker
     15 Hz, band to 60 Hz), one shot and two of its receivers, offsets up to
     16 cells: sampled (x, h) against traces of the same engine (property of
@@ -136,8 +143,8 @@ def test_offset_diag_exact_full_size_reciprocity():
     rec = np.array([100, 900], np.int32)     # receivers at ix 200 and 1800
     geom = Geometry(g.src_iz, g.src_ix, np.array([0, 2], np.int32), g.rec_iz[rec], g.rec_ix[rec], g.nt)
     hmax, fmax = 16, 60.0
-    ex = B.make_exec(shots_in_flight=1)
-    D = cpu(B.offset_diag_exact(w.v_start, w.wavelet, grid, geom, hmax, fmax, ex))
+    ex = B.make_exec(shots_in_flight=2)
+    D = cpu(B.offset_diag_exact(w.v_start, w.wavelet, grid, geom, hmax, fmax, ex, dft=DFTS[dft]))
     torch.cuda.empty_cache()
     nt = int(geom.nt[0])
     L = 2 * nt
@@ -165,4 +172,4 @@ def test_offset_diag_exact_full_size_reciprocity():
             want += float(np.sum(m * PA * PB)) / L
         want *= 4.0 / float(w.v_start[iz, ix]) ** 6
         got = float(D[h + hmax, iz, ix])
-        assert report(f"exact diag 2048x768 (z {iz}, x {ix}, h {h})", abs(got / want - 1.0), GRAD_TOL) < GRAD_TOL
+        assert report(f"exact diag 2048x768 {dft} (z {iz}, x {ix}, h {h})", abs(got / want - 1.0), GRAD_TOL) < GRAD_TOL
