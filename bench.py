@@ -60,6 +60,7 @@ def parse():
                     help="also time the offset diagonal with the exact receiver term on the first "
                          "--exact-shots shots and EXACT_DIAG of their receivers (band to 4 f_peak)")
     ap.add_argument("--exact-shots", type=int, default=2)
+    ap.add_argument("--exact-sif", type=int, default=4, help="runs in flight of the exact offset diagonal")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
                          "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps]")
@@ -198,10 +199,10 @@ FP32_MFMA_PEAK_TFS = 157.3
 def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     """fwi_offset_diag_exact on a subset: the first shots and an evenly spread
     subset of their receivers (one group), band up to 4 f_peak, |h| <= 16,
-    8 runs in flight, with each DFT arithmetic.  Each run (a receiver's
-    impulse response or a shot) is a forward sweep that captures the model
-    cells' series 1024 updates at a time, each chunk folded into the run's
-    spectra by a GEMM with the DFT matrix."""
+    --exact-sif runs in flight, with each DFT arithmetic.  Each run (a
+    receiver's impulse response or a shot) is a forward sweep that captures
+    the model cells' series 8192 / runs-in-flight updates at a time, each
+    chunk folded into the run's spectra by a GEMM with the DFT matrix."""
     import torch
     from paper_1406_1864_amd import binding as B
     from paper_1406_1864_amd.synthetic import Geometry
@@ -212,7 +213,7 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
                    (np.arange(ns + 1) * len(keep)).astype(np.int32),
                    np.tile(geom.rec_iz[keep], ns), np.tile(geom.rec_ix[keep], ns), geom.nt[:ns].copy())
     hmax, fmax = 16, 4.0 * w.f_peak
-    ex = B.make_exec(shots_in_flight=8)
+    ex = B.make_exec(shots_in_flight=args.exact_sif)
     runs = ns + len(keep)
     nt = int(sub.nt[0])
     L = 2 * nt
@@ -220,9 +221,10 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     model = grid.nz * grid.nx
     Z, X = grid.padded
     gemm_flop = 2.0 * model * (nt - 1) * 2 * K          # per run, FP32-equivalent
+    chunk = min(nt - 1, max(64, 8192 // min(args.exact_sif, runs) // 64 * 64))
     full_runs = full_shots + (b - a)
     out = {"unit": "runs/s (forward sweep with series capture + DFT GEMM)", "shots": ns,
-           "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": 8,
+           "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": args.exact_sif, "chunk": chunk,
            "gemm_shape_per_run": [model, 2 * K, nt - 1], "gemm_tflop_per_run": gemm_flop / 1e12,
            "cell_updates_per_run": float(Z * X * (nt - 1)), "full_problem_runs": full_runs}
     Dref = None

@@ -327,7 +327,8 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  *
  * Shots are grouped by (record length, receiver set); each group costs one
  * forward run per receiver and per shot, shots_in_flight runs at a time
- * (default 8).  A run's series are captured 1024 updates at a time and folded
+ * (default 4).  A run's series are captured 8192 / shots_in_flight updates at
+ * a time (a multiple of 64, at least 64) and folded
  * into its spectra by a GEMM with the DFT matrix (rocBLAS), in FP32 (dft =
  * FWI_DFT_FP32) or as three bf16 products with FP32 accumulation of the
  * series and the DFT matrix split into bf16 pairs (FWI_DFT_BF16X3: about 16

@@ -1183,9 +1183,14 @@ struct DxLayout {
   int lg = 0, nblk = 0;   // GEMM row blocks of 2^lg model cells
 };
 
-// steps captured per chunk: the captured series of S runs take S Tc model
-// cells of 4 bytes (FP32, or a bf16 pair)
-constexpr int kDxChunk = 1024;
+// Run-steps held by the chunk buffer: S runs in flight capture Tc = 8192 / S
+// updates (a multiple of 64) per chunk, so that fewer runs in flight buy
+// longer chunks and fewer read-modify-write passes over the spectra
+constexpr int kDxRunSteps = 8192;
+// default runs in flight: at 2048x768, nt 8000, 4 runs with 2048-update
+// chunks took 138 ms per run (bf16 split), 2 / 3 / 8 / 16 runs 187 / 158 /
+// 156 / 171 ms: fewer runs starve the sweeps, more shorten the chunks
+constexpr int kDxRuns = 4;
 
 // The GEMMs take blocks of at most 2^16 model cells as batch entries, so
 // that every operand offset inside one entry stays far below 2^31 elements
@@ -1287,7 +1292,7 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
   if (!(fmax >= 0) || !std::isfinite(fmax)) return fail(FWI_ERR_ARG, "fmax must be finite and >= 0");
   if (dft != FWI_DFT_FP32 && dft != FWI_DFT_BF16X3) return fail(FWI_ERR_ARG, "dft must be FWI_DFT_FP32 or FWI_DFT_BF16X3");
   const int64_t model = (int64_t)g->nz * g->nx;
-  const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : 8;
+  const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : kDxRuns;
   o = DxLayout{};
   int Smax = 1, nshot_max = 1;
   for (const DxGroup& gr : dx_groups(g, geo)) {
@@ -1305,7 +1310,7 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
     }
   }
   o.S = Smax;
-  o.Tc = std::max(1, std::min(o.Tn, kDxChunk));
+  o.Tc = std::max(1, std::min(o.Tn, std::max(64, kDxRunSteps / Smax / 64 * 64)));
   dx_blocks(model, o.lg, o.nblk);
   const size_t rows = (size_t)o.nblk << o.lg;  // model cells padded to whole blocks
   size_t off = align_up(o.plan);
@@ -1719,7 +1724,7 @@ int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const 
   // the impulse [1, 0, 0, ...] that starts a receiver's response
   HIP_TRY(launch_fill(imp, sizeof(float) * grid->nt_max, s));
   HIP_TRY(launch_set((int32_t*)imp, 0x3f800000, s));
-  const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : 8;
+  const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : kDxRuns;
   // C[e] (+)= X[e] . Wq for chunk q (updates k0 .. k0+tc-1) and every entry
   // e (slot, block of mb cells): FP32, X the chunk's series (mb x tc, ld mb)
   // and Wq rows k0 .. of the DFT matrix (ld ldw); split, [Xh | Xl | Xh]

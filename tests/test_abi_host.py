@@ -233,9 +233,10 @@ def test_offset_diag_exact_sizing_and_rejects(lib):
 
 
 def test_offset_diag_exact_fits_an_mi355x_at_full_size(lib):
-    """2048x768, nt 8000, band to 60 Hz, 8 runs in flight: the captured
-    chunks and the spectra fit in 288 GB."""
+    """2048x768, nt 8000, band to 60 Hz, the default 4 runs in flight and 8:
+    the captured chunks and the spectra fit in 288 GB."""
     w = offset_2048x768()
-    for dft in (B.DFT_FP32, B.DFT_BF16X3):
-        n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, B.make_exec(shots_in_flight=8), 16, 60.0, dft)
-        assert 0 < n < 150e9, (dft, n)
+    for ex in (None, B.make_exec(shots_in_flight=8)):
+        for dft in (B.DFT_FP32, B.DFT_BF16X3):
+            n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, ex, 16, 60.0, dft)
+            assert 0 < n < 150e9, (dft, n)
