@@ -251,7 +251,35 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
         del ws, D
         torch.cuda.empty_cache()
     out["value"] = out["bf16x3"]["value"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_offset_diag_exact(w, grid, sub, fmax)
     return out
+
+
+def cpu_baseline_offset_diag_exact(w, grid, geom, fmax, nsteps=48, ncells=4096):
+    """The FP64 oracle's cost of one run of the exact offset diagonal, on a
+    bounded sample: its impulse-response modelling (green_series) over the
+    first `nsteps` updates of the full grid, and its L-point spectra (power)
+    of `ncells` full-length series; both extrapolated linearly to a whole run
+    (every update, every model cell)."""
+    import oracle
+    from paper_1406_1864_amd.synthetic import Grid
+    nt = int(geom.nt[0])
+    g = Grid(grid.nz, grid.nx, grid.dx, grid.dt, nsteps, grid.nsponge, grid.v_ref)
+    t0 = time.perf_counter()
+    oracle.green_series(w.v_start, g, int(geom.rec_iz[0]), int(geom.rec_ix[0]), nsteps)
+    t_fwd = time.perf_counter() - t0
+    L, K, _ = oracle.spectral_bins(nt, grid.dt, fmax)
+    x = np.random.default_rng(0).standard_normal((nt - 1, ncells))
+    t0 = time.perf_counter()
+    oracle.power(x, L, K)
+    t_dft = time.perf_counter() - t0
+    per_run = t_fwd * (nt - 1) / (nsteps - 1) + t_dft * (grid.nz * grid.nx) / ncells
+    return {"value": 1.0 / per_run, "unit": "runs/s", "cores": 1, "kind": "oracle",
+            "seconds": t_fwd + t_dft,
+            "sample": f"green_series over the first {nsteps} of {nt} updates of the full grid and power() of "
+                      f"{ncells} of {grid.nz * grid.nx} cells' {nt - 1}-sample series (FP64 NumPy, single "
+                      f"thread), extrapolated linearly to one whole run"}
 
 
 def main():
