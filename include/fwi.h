@@ -320,7 +320,7 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  *               response at r to a unit source term at y), n = 0 .. nt-2,
  * h_g the grid spacing, m_0 = 1, m_k = 2, and m = 1 for the Nyquist bin
  * k = nt.  fmax > 0 keeps the bins k <= fmax L dt (frequencies up to fmax
- * Hz); fmax = 0 keeps all nt + 1 of them.  With every bin this is the norm of
+ * Hz); fmax = 0 keeps all nt + 1 of them (at most 65535 bins).  With every bin this is the norm of
  * the extended-Born column of (x, h) over the whole response (conventional
  * misfit).  Horizontal offsets |h| <= hmax <= 32; terms with x+h or x-h
  * outside the model are 0.

@@ -1298,6 +1298,8 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
   for (const DxGroup& gr : dx_groups(g, geo)) {
     int L, K, nyq;
     dx_bins(gr.nt, g->dt, fmax, L, K, nyq);
+    // the power kernel takes the bins as its grid's second dimension
+    if (K > 65535) return fail(FWI_ERR_ARG, "more than 65535 frequency bins: bound the band with fmax");
     o.Tn = std::max(o.Tn, gr.nt - 1);
     o.K = std::max(o.K, K);
     nshot_max = std::max(nshot_max, (int)gr.shots.size());

@@ -225,6 +225,10 @@ def test_offset_diag_exact_sizing_and_rejects(lib):
     with pytest.raises(B.FwiError) as e:
         B.fwi_offset_diag_exact(g, geo, None, fake, fake, 0, 4, 0.0, 3, fake, fake, 1 << 40, stream=0)
     assert e.value.code == B.FWI_ERR_ARG
+    long = Grid(g.nz, g.nx, g.dx, g.dt, 70000, g.nsponge, g.v_ref)
+    lgeo = Geometry(geo.src_iz, geo.src_ix, geo.rec_ptr, geo.rec_iz, geo.rec_ix, np.full(2, 70000, np.int32))
+    assert B.fwi_offset_diag_exact_workspace_bytes(long, lgeo, None, 4, 0.0) == 0       # 70001 bins
+    assert B.fwi_offset_diag_exact_workspace_bytes(long, lgeo, None, 4, 60.0) > 0       # 8401 bins
     g.free_surface = True
     assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0) == 0
     with pytest.raises(B.FwiError) as e:
