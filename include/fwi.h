@@ -33,7 +33,10 @@
  *     HIP device memory on the current device.  Geometry arrays inside
  *     fwi_geometry are HOST pointers; they are read during the call only.
  *   - The library never allocates device memory: all scratch lives in the
- *     caller's workspace, sized by fwi_workspace_bytes().
+ *     caller's workspace, sized by fwi_workspace_bytes().  One exception:
+ *     fwi_offset_diag_exact runs its DFT GEMMs through rocBLAS, whose
+ *     per-device handle (created on the first call) manages its own device
+ *     memory and may allocate on a call with new GEMM shapes.
  *   - Calls are asynchronous on `hip_stream` (a hipStream_t, NULL = default
  *     stream).  Do not run two calls concurrently on the same workspace.
  *   - Return 0 on success or a negative FWI_ERR_* code.  Every host-side check
