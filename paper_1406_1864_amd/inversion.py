@@ -4,9 +4,13 @@ Section 2.1 inverts with limited-memory BFGS and section 3.1 with
 preconditioned conjugate gradients, comparing three scalings of the gradient:
 none, the shot illumination of eq. (1) (P = (4/v^6) H1) and the diagonal of
 the localized subsurface-offset Hessian of section 3 (P = sum_h D(x, h)), each
-applied as g / (P + eps max P).  This module provides both drivers and a
-GPU objective that evaluates J, dJ/dv and the scaling through the HIP
-library (fwi_misfit_value, fwi_gradient, fwi_precondition).
+applied as g / (P + eps max P).  The offset diagonal is taken with the
+aperture-factor receiver model ("offset") or with the exact receiver term
+from the receivers' impulse responses ("offset_exact", the conventional
+misfit's diagonal, band up to `fmax` Hz).  This module provides both drivers
+and a GPU objective that evaluates J, dJ/dv and the scaling through the HIP
+library (fwi_misfit_value, fwi_gradient, fwi_offset_diag_exact,
+fwi_precondition).
 
 The drivers are plain host logic on NumPy arrays over any objective with
 
@@ -32,10 +36,10 @@ class GPUObjective:
     """J(v), dJ/dv and the diagonal scaling on the device, NumPy in and out."""
 
     def __init__(self, grid, geom, wavelet, d_obs, misfit="int", precond="shot", hmax=8, eps=1e-2,
-                 rcv_model="pm", exec_=None, device="cuda"):
+                 rcv_model="pm", exec_=None, device="cuda", fmax=0.0, exact_runs=32):
         import torch
         from . import binding as B
-        if precond not in ("none", "shot", "offset"):
+        if precond not in ("none", "shot", "offset", "offset_exact"):
             raise ValueError(precond)
         self.B, self.torch = B, torch
         self.grid, self.geom = grid, B.GeometryC(geom)
@@ -47,6 +51,13 @@ class GPUObjective:
         self.ws_f = B.workspace(grid, self.geom, B.WS_FORWARD, exec_, device=device)
         self.ws_g = B.workspace(grid, self.geom, B.WS_GRADIENT, exec_, hmax if precond == "offset" else 0,
                                 device=device)
+        if precond == "offset_exact":
+            self.fmax = fmax
+            self.ex_x = B.make_exec(shots_in_flight=exact_runs)
+            n = B.fwi_offset_diag_exact_workspace_bytes(grid, self.geom, self.ex_x, hmax, fmax, B.DFT_BF16X3)
+            if n == 0:
+                raise B.FwiError(B.FWI_ERR_ARG, B.last_error())
+            self.ws_x = torch.empty(n, dtype=torch.uint8, device=device)
         self.evals = 0
         self.grads = 0
 
@@ -71,6 +82,10 @@ class GPUObjective:
              if self.precond == "offset" else None)
         B.fwi_gradient(self.grid, self.geom, self.exec, vd, self.wavelet, self.wstride, self.d_obs, self.misfit,
                        J, grad, H1, self.hmax if D is not None else 0, self.rcv, D, self.ws_g, self.ws_g.numel())
+        if self.precond == "offset_exact":
+            D = t.empty((2 * self.hmax + 1, g_.nz, g_.nx), dtype=t.float32, device=self.device)
+            B.fwi_offset_diag_exact(self.grid, self.geom, self.ex_x, vd, self.wavelet, self.wstride, self.hmax,
+                                    self.fmax, B.DFT_BF16X3, D, self.ws_x, self.ws_x.numel())
         if self.precond == "none":
             minv = np.ones((g_.nz, g_.nx))
         else:
@@ -195,7 +210,7 @@ def main():
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--method", choices=["prcg", "lbfgs"], default="prcg")
     ap.add_argument("--misfits", default="l2,int")
-    ap.add_argument("--preconds", default="none,shot,offset")
+    ap.add_argument("--preconds", default="none,shot,offset,offset_exact")
     args = ap.parse_args()
     w = layered_256x96()
     d_obs = B.forward(w.v_true, w.wavelet, w.grid, w.geom)
@@ -203,7 +218,7 @@ def main():
     out = []
     for misfit in args.misfits.split(","):
         for pc in args.preconds.split(","):
-            obj = GPUObjective(w.grid, w.geom, w.wavelet, d_obs, misfit, pc, hmax=w.hmax)
+            obj = GPUObjective(w.grid, w.geom, w.wavelet, d_obs, misfit, pc, hmax=w.hmax, fmax=4.0 * w.f_peak)
             t0 = time.perf_counter()
             run = prcg if args.method == "prcg" else lbfgs
             v, hist = run(obj, w.v_start, args.iters)

@@ -38,14 +38,16 @@ class OracleObjective:
         else:
             if self.precond == "shot":
                 P = oracle.shot_scaling(v, H1)
-            else:
+            elif self.precond == "offset":
                 A = [oracle.aperture_factor(w.grid, *w.geom.shot(s)[2:4]) for s in range(w.geom.nshot)]
                 P = oracle.offset_scaling(oracle.offset_diag(v, E, A, self.hmax))
+            else:
+                P = oracle.offset_scaling(oracle.offset_diag_spectral(v, w.grid, w.geom, w.wavelet, self.hmax))
             minv = oracle.precondition(np.ones_like(g), P, self.eps)
         return J, g, minv
 
 
-@pytest.mark.parametrize("precond", ["none", "shot", "offset"])
+@pytest.mark.parametrize("precond", ["none", "shot", "offset", "offset_exact"])
 @pytest.mark.parametrize("driver", [prcg, lbfgs])
 def test_two_iterations_match_the_oracle(precond, driver):
     w = tiny_24x16(nt=300)
