@@ -173,3 +173,28 @@ def test_offset_diag_exact_full_size_reciprocity(dft):
         want *= 4.0 / float(w.v_start[iz, ix]) ** 6
         got = float(D[h + hmax, iz, ix])
         assert report(f"exact diag 2048x768 {dft} (z {iz}, x {ix}, h {h})", abs(got / want - 1.0), GRAD_TOL) < GRAD_TOL
+
+
+def test_aperture_factor_reading_against_exact_receiver_term():
+    """Diagnostic (parity unpinned: the paper prints no numbers for it): how
+    closely the aperture-factor reading of the offset diagonal (Plessix-Mulder
+    receiver factor, or none) follows the diagonal with the exact receiver
+    term, on the 200x100 anomaly workload (1 shot, 100 receivers, |h| <= 8).
+    Reported: the correlation of the two over all (x, h), and the relative gap
+    after the best single scale factor (the two differ in normalisation).
+    Asserted: both finite, positive where illuminated, positively correlated."""
+    w = anomaly_200x100()
+    hmax = 8
+    exact = cpu(B.offset_diag_exact(w.v_start, w.wavelet, w.grid, w.geom, hmax, 4.0 * w.f_peak)).astype(np.float64)
+    assert np.all(np.isfinite(exact)) and np.all(exact >= 0) and exact.max() > 0
+    for rcv in ("pm", "none"):
+        pm = cpu(B.hessian_diag(w.v_start, w.wavelet, w.grid, w.geom, B.HESS_OFFSET, hmax, rcv)).astype(np.float64)
+        assert np.all(np.isfinite(pm))
+        a, b = pm.ravel(), exact.ravel()
+        corr = float(np.corrcoef(a, b)[0, 1])
+        scale = float(a @ b / (a @ a))
+        gap = float(np.linalg.norm(scale * a - b) / np.linalg.norm(b))
+        c0 = float(np.corrcoef(pm[hmax].ravel(), exact[hmax].ravel())[0, 1])
+        print(f"[diagnostic] offset diagonal, receiver model {rcv} vs exact (200x100, |h| <= {hmax}): "
+              f"correlation {corr:.3f} (h = 0: {c0:.3f}), relative gap after scaling {gap:.3f}", flush=True)
+        assert corr > 0
