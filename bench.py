@@ -441,7 +441,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": rev_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch, "launches": launches,
-                     "avg_launch_us": launch_us},
+                     "avg_launch_us": launch_us,
+                     # per padded cell and time step of one shot, and the measured rate
+                     "algorithmic_bytes_per_cell_step": bytes_per_launch / (Sr * RS * Z * X),
+                     "measured_bytes_per_cell_step": traffic / (Sr * RS * Z * X) if traffic else None,
+                     "measured_GBps": traffic / (launch_us * 1e-6) / 1e9 if traffic else None},
         "copy_GBps": copy_gbs,
         "forward_roofline": {"achieved": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9, "unit": "GB/s",
                              "frac": fwd_bytes / (phase[0] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
