@@ -198,3 +198,20 @@ def test_aperture_factor_reading_against_exact_receiver_term():
         print(f"[diagnostic] offset diagonal, receiver model {rcv} vs exact (200x100, |h| <= {hmax}): "
               f"correlation {corr:.3f} (h = 0: {c0:.3f}), relative gap after scaling {gap:.3f}", flush=True)
         assert corr > 0
+
+
+def test_offset_diag_exact_groups_by_record_length():
+    """Three shots with the same receivers, two record lengths (two groups,
+    one of them with two shots), per-shot wavelets, zero offset only."""
+    w = tiny_24x16(nt=260)
+    g = w.geom
+    rec = np.arange(2, 24, 4)
+    geom = Geometry(np.array([1, 1, 3], np.int32), np.array([3, 20, 11], np.int32),
+                    np.array([0, 6, 12, 18], np.int32), np.full(18, 1, np.int32),
+                    np.tile(rec, 3).astype(np.int32), np.array([260, 180, 260], np.int32))
+    wav = np.stack([w.wavelet, 0.5 * w.wavelet, np.roll(w.wavelet, 7)]).astype(np.float32)
+    ref = oracle.offset_diag_spectral(w.v_start, w.grid, geom, wav, 0, fmax=50.0)
+    for dft in DFTS:
+        got = B.offset_diag_exact(w.v_start, wav, w.grid, geom, 0, 50.0, B.make_exec(shots_in_flight=2),
+                                  dft=DFTS[dft])
+        check(f"two record lengths, h = 0 only, {dft}", ref, got, 0)
