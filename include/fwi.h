@@ -323,23 +323,24 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  *               response at r to a unit source term at y), n = 0 .. nt-2,
  * h_g the grid spacing, m_0 = 1, m_k = 2, and m = 1 for the Nyquist bin
  * k = nt.  fmax > 0 keeps the bins k <= fmax L dt (frequencies up to fmax
- * Hz); fmax = 0 keeps all nt + 1 of them (at most 65535 bins).  With every bin this is the norm of
- * the extended-Born column of (x, h) over the whole response (conventional
- * misfit).  Horizontal offsets |h| <= hmax <= 32; terms with x+h or x-h
- * outside the model are 0.
+ * Hz); fmax = 0 keeps all nt + 1 of them (at most 65535 bins).  With every
+ * bin this is the norm of the extended-Born column of (x, h) over the whole
+ * response (conventional misfit).  Horizontal offsets |h| <= hmax <= 32;
+ * terms with x+h or x-h outside the model are 0.
  *
  * Shots are grouped by (record length, receiver set); each group costs one
  * forward run per receiver and per shot, shots_in_flight runs at a time
  * (default 4; of exec only shots_in_flight, tile_rows and prefetch are used:
- * the sweeps are direct one-step launches, not graphs, and not autotuned).  A run's series are captured 8192 / shots_in_flight updates at
- * a time (a multiple of 64, at least 64) and folded
- * into its spectra by a GEMM with the DFT matrix (rocBLAS), in FP32 (dft =
- * FWI_DFT_FP32) or as three bf16 products with FP32 accumulation of the
- * series and the DFT matrix split into bf16 pairs (FWI_DFT_BF16X3: about 16
- * significant bits per product, the lo*lo term dropped).  The workspace holds
- * the chunks and spectra of the runs in flight: see
- * fwi_offset_diag_exact_workspace_bytes (0 on bad arguments).  Not with a
- * free surface.  diag: device [2 hmax + 1][nz][nx], overwritten. */
+ * the sweeps are direct one-step launches, not graphs, and not autotuned).
+ * A run's series are captured 8192 / shots_in_flight updates at a time (a
+ * multiple of 64, at least 64) and folded into its spectra by a GEMM with
+ * the DFT matrix (rocBLAS), in FP32 (dft = FWI_DFT_FP32) or as three bf16
+ * products with FP32 accumulation of the series and the DFT matrix split
+ * into bf16 pairs (FWI_DFT_BF16X3: about 16 significant bits per product,
+ * the lo*lo term dropped).  The workspace holds the chunks and spectra of
+ * the runs in flight: see fwi_offset_diag_exact_workspace_bytes (0 on bad
+ * arguments).  Not with a free surface.  diag: device [2 hmax + 1][nz][nx],
+ * overwritten. */
 enum { FWI_DFT_FP32 = 0, FWI_DFT_BF16X3 = 1 };
 size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
                                              const fwi_exec *exec, int hmax, double fmax, int dft);
