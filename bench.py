@@ -61,6 +61,8 @@ def parse():
                          "--exact-shots shots and EXACT_DIAG of their receivers (band to 4 f_peak)")
     ap.add_argument("--exact-shots", type=int, default=2)
     ap.add_argument("--exact-sif", type=int, default=4, help="runs in flight of the exact offset diagonal")
+    ap.add_argument("--exact-dft", choices=["both", "fp32", "bf16x3"], default="both",
+                    help="DFT arithmetic(s) timed for the exact offset diagonal")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
                          "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps]")
@@ -199,7 +201,8 @@ FP32_MFMA_PEAK_TFS = 157.3
 def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     """fwi_offset_diag_exact on a subset: the first shots and an evenly spread
     subset of their receivers (one group), band up to 4 f_peak, |h| <= 16,
-    --exact-sif runs in flight, with each DFT arithmetic.  Each run (a
+    --exact-sif runs in flight, with the DFT arithmetic(s) of --exact-dft
+    (the untimed first call only with --warmup > 0).  Each run (a
     receiver's impulse response or a shot) is a forward sweep that captures
     the model cells' series 8192 / runs-in-flight updates at a time, each
     chunk folded into the run's spectra by a GEMM with the DFT matrix."""
@@ -227,20 +230,23 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
            "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": args.exact_sif, "chunk": chunk,
            "gemm_shape_per_run": [model, 2 * K, nt - 1], "gemm_tflop_per_run": gemm_flop / 1e12,
            "cell_updates_per_run": float(Z * X * (nt - 1)), "full_problem_runs": full_runs}
-    Dref = None
-    for name, dft in (("fp32", B.DFT_FP32), ("bf16x3", B.DFT_BF16X3)):
+    Dref = D = None
+    modes = [m for m in (("fp32", B.DFT_FP32), ("bf16x3", B.DFT_BF16X3)) if args.exact_dft in ("both", m[0])]
+    for name, dft in modes:
+        print(f"# exact offset diagonal, {name}: {runs} runs", file=sys.stderr, flush=True)
         nbytes = B.fwi_offset_diag_exact_workspace_bytes(grid, sub, ex, hmax, fmax, dft)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         fn = lambda: B.offset_diag_exact(w.v_start, w.wavelet, grid, sub, hmax, fmax, ex, ws=ws, device=dev,
                                          dft=dft)
-        D = fn()
+        if args.warmup > 0:                 # untimed first call
+            D = fn()
         torch.cuda.synchronize()
-        assert bool(torch.isfinite(D).all())
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            fn()
+            D = fn()
         torch.cuda.synchronize()
         call = (time.perf_counter() - t0) / args.steps
+        assert bool(torch.isfinite(D).all())
         r = {"value": runs / call, "ms_per_call": 1e3 * call, "ms_per_run": 1e3 * call / runs,
              "workspace_gb": nbytes / 1e9, "full_problem_s_extrapolated": full_runs * call / runs}
         if Dref is None:
@@ -248,9 +254,24 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
         else:
             r["rel_l2_vs_fp32"] = float(torch.linalg.norm(D.double() - Dref) / torch.linalg.norm(Dref))
         out[name] = r
-        del ws, D
+        del ws
         torch.cuda.empty_cache()
-    out["value"] = out["bf16x3"]["value"]
+    out["value"] = out[modes[-1][0]]["value"]
+    # the aperture-factor reading of the same diagonal (fwi_hessian_diag), its
+    # cost and how closely it follows the exact receiver term
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = B.hessian_diag(w.v_start, w.wavelet, grid, sub, B.HESS_OFFSET, hmax, "pm", device=dev)
+    torch.cuda.synchronize()
+    pa, pb = P.double().flatten(), D.double().flatten()
+    am, bm = pa - pa.mean(), pb - pb.mean()
+    scale = float(pa @ pb / (pa @ pa))
+    out["aperture_factor_reading"] = {
+        "seconds": time.perf_counter() - t0,
+        "correlation_with_exact": float(am @ bm / (am.norm() * bm.norm())),
+        "rel_l2_gap_after_scaling": float((scale * pa - pb).norm() / pb.norm())}
+    del D, Dref, P
+    torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_offset_diag_exact(w, grid, sub, fmax)
     return out
