@@ -1,17 +1,21 @@
 """Shared tolerances and error measures of the GPU parity tests.
 
 Seismograms: relative L2 <= 1e-4; gradients and Hessian diagonals: relative
-L2 <= 1e-3 (the accuracy contract of the hot path).  J has no contract of its
-own: it is a function of the seismograms, so its tolerance is derived from
-the seismogram tolerance.  With W the misfit's data weighting (identity, or
-dt times the running sum for eq. (2)) and r = d_syn - d_obs,
-|J' - J| <= |<W r, W e>| + |W e|^2 / 2 <= tol |W d_syn| |W r| + ...,
-so |dJ| / J <= 2 tol |W d_syn| / |W r| to first order.
+L2 <= 1e-3 (the accuracy contract of the hot path).  J: relative error
+<= 1e-4.  J is a function of the seismograms; to first order
+|dJ| / J <= 2 e |W d_syn| / |W r| for a relative trace error e (W the
+misfit's data weighting, r the residual), which for the FP32 traces
+(e ~ 1e-6) stays below 1e-4 on every case here, the ill-conditioned
+anomaly residual (|r| / |d| = 0.4 %) included.  A gate derived from the
+1e-4 trace tolerance instead would allow a few per cent on those cases and
+miss a bug confined to the misfit reduction (a dropped sample of the
+running sum, say).
 """
 import numpy as np
 
 TRACE_TOL = 1e-4
 GRAD_TOL = 1e-3
+J_TOL = 1e-4
 
 
 def rel(a, b):
@@ -20,16 +24,24 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def max_rel(a, b):
+    """Largest element-wise deviation relative to the reference's largest
+    magnitude: max |a - b| / max |b| (catches an error confined to a few
+    cells, which the relative L2 over a large array dilutes)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
 def weight(x, kind, dt):
     x = np.asarray(x, np.float64)
     return dt * np.cumsum(x, axis=-1) if kind in ("int", 1) else x
 
 
-def j_tolerance(d_syn, d_obs, kind, dt):
-    """Relative tolerance on J implied by TRACE_TOL on the synthetic traces."""
-    Wd = weight(d_syn, kind, dt)
-    Wr = weight(np.asarray(d_syn, np.float64) - d_obs, kind, dt)
-    return 2.0 * TRACE_TOL * np.linalg.norm(Wd) / np.linalg.norm(Wr)
+def j_tolerance(d_syn=None, d_obs=None, kind=None, dt=None):
+    """Relative tolerance on J (fixed; the arguments are accepted so that
+    every caller names the case it checks)."""
+    return J_TOL
 
 
 def report(name, err, tol):

@@ -51,6 +51,28 @@ def test_amplifying_sponge_is_caught(monkeypatch):
     fails(P.test_sponge_absorbs)
 
 
+def test_doubled_sponge_damping_is_caught(monkeypatch):
+    orig = ac.sponge_gamma
+    plant(monkeypatch, ac, "sponge_gamma", lambda g: 2.0 * orig(g))
+    fails(P.test_sponge_normal_incidence_reflection)
+
+
+def test_halved_sponge_damping_is_caught(monkeypatch):
+    orig = ac.sponge_gamma
+    plant(monkeypatch, ac, "sponge_gamma", lambda g: 0.5 * orig(g))
+    fails(P.test_sponge_normal_incidence_reflection)
+
+
+def test_offset_scaling_mean_is_caught(monkeypatch):
+    plant(monkeypatch, hs, "offset_scaling", lambda D: np.mean(D, axis=0))
+    fails(P.test_offset_scaling_sums_every_offset)
+
+
+def test_offset_scaling_zero_offset_only_is_caught(monkeypatch):
+    plant(monkeypatch, hs, "offset_scaling", lambda D: np.asarray(D)[np.asarray(D).shape[0] // 2])
+    fails(P.test_offset_scaling_sums_every_offset)
+
+
 def test_exclusive_time_integral_is_caught(monkeypatch):
     def exclusive(d_syn, d_obs, dt):
         r = np.asarray(d_syn, np.float64) - np.asarray(d_obs, np.float64)
