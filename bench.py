@@ -9,19 +9,21 @@ epilogue and the preconditioned gradient, driven through torch.autograd
 (J.backward()).
 
 Workloads (--workload):
-  layered  (default) 1024x384 layered model, 64 shots, 512 receivers each,
-           nt = 4000, dt = 1 ms, Ricker 8 Hz; H1 and the offset diagonal
-           |h| <= 16; shot-scaling preconditioner
-  ragged   same model, 256 shots of 128..1024 receivers and nt 2000..6000; H1;
+  offset   (default) 2048x768 layered model at dx = 6.25 m, 32 shots, 1024
+           receivers each, nt = 8000, dt = 0.5 ms, Ricker 15 Hz; H1 and the
+           offset diagonal |h| <= 16; sub-offset Hessian preconditioner (the
+           largest configuration, the batched autograd preconditioned
+           gradient of section 3)
+  layered  1024x384 at dx = 12.5 m, 64 shots, 512 receivers each, nt = 4000,
+           dt = 1 ms, Ricker 8 Hz; H1 and the offset diagonal |h| <= 16;
            shot-scaling preconditioner
-  offset   2048x768 at dx = 6.25 m, 32 shots, 1024 receivers, nt = 8000,
-           dt = 0.5 ms, Ricker 15 Hz; H1 and the offset diagonal |h| <= 16;
-           sub-offset Hessian preconditioner
+  ragged   the 1024x384 model, 256 shots of 128..1024 receivers and nt
+           2000..6000; H1; shot-scaling preconditioner
 
 Prints one JSON line.  `value` is shot-gradients per second; the line also
 carries Gcell-updates/s, the roofline of the dominant kernel (the fused
 reverse step), the plain per-shot GPU path on a subset of shots, and the FP64
-oracle timed on the host on a bounded sample.
+oracle timed on the host's cores on a bounded sample.
 """
 import argparse
 import hashlib
@@ -43,13 +45,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["layered", "ragged", "offset"], default="layered")
+    ap.add_argument("--workload", choices=["layered", "ragged", "offset"], default="offset")
     ap.add_argument("--shots", type=int, default=0, help="use only the first SHOTS shots (0 = all)")
     ap.add_argument("--plain-shots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
-                    help="time steps of the oracle sample (0 = about 15 s of host work)")
+                    help="time steps of each worker's oracle sample (0 = about 15 s of work per worker)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle worker processes (0 = the cores this process may use, at most 16)")
     ap.add_argument("--nt", type=int, default=0,
                     help="shorten every record to NT samples (counter-collection runs; 0 = full)")
     ap.add_argument("--ext", type=int, default=-1,
@@ -101,12 +105,21 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kname, chosen):
+# synthetic.WORKLOADS name of each benchmark workload
+WNAME = {"layered": "layered_1024x384", "ragged": "ragged_1024x384", "offset": "offset_2048x768"}
+# grid tag of the committed counter summaries, per workload
+PMC_TAG = {"layered": "layered_1024x384", "offset": "layered_2048x768"}
+
+
+def measured_traffic(kname, chosen, workload):
     """HBM bytes per launch of `kname` from the committed rocprofv3 counter
-    summary (FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy), or None when that
-    summary was taken on other kernel source or with other settings of the
-    reverse launches (the forward settings leave that kernel's bytes alone)."""
-    path = os.path.join(ROOT, "profiles", f"{kname}_pmc_layered_1024x384.json")
+    summary of this workload (FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy),
+    or None when there is none, or it was taken on other kernel source or
+    with other settings of the reverse launches (the forward settings leave
+    that kernel's bytes alone)."""
+    if workload not in PMC_TAG:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{kname}_pmc_{PMC_TAG[workload]}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -120,24 +133,93 @@ def measured_traffic(kname, chosen):
     return p.get("bytes_per_launch")
 
 
-def cpu_baseline(w, nsteps):
-    """The FP64 oracle as it stands, one shot, first `nsteps` time steps."""
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+_WORKER_WORKLOADS = {}
+
+
+def _init_oracle_worker(names):
+    """Builds the workloads once per worker process, outside the timed work."""
+    import oracle  # noqa: F401
+    from paper_1406_1864_amd.synthetic import WORKLOADS
+    for name in names:
+        _WORKER_WORKLOADS[name] = WORKLOADS[name]()
+
+
+def _oracle_shot_sample(job):
+    """One task of the CPU baseline: the FP64 oracle's gradient of shot `s`
+    of workload `name` over the first `nsteps` time steps (the whole record
+    when nsteps >= its length).  Returns (seconds, steps timed, record length)."""
+    name, s, nsteps = job
     import oracle
     from paper_1406_1864_amd.synthetic import Grid
-    geom = w.geom.subset([0]).with_nt(nsteps)
-    grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, nsteps, w.grid.nsponge, w.grid.v_ref)
-    d_obs = np.zeros((geom.ntrace, nsteps), np.float32)
+    w = _WORKER_WORKLOADS[name]
+    nt_full = int(w.geom.nt[s])
+    n = min(nsteps, nt_full)
+    geom = w.geom.subset([s]).with_nt(n)
+    grid = Grid(w.grid.nz, w.grid.nx, w.grid.dx, w.grid.dt, n, w.grid.nsponge, w.grid.v_ref)
+    d_obs = np.zeros((geom.ntrace, n), np.float32)
     t0 = time.perf_counter()
-    oracle.gradient(w.v_start, grid, geom, w.wavelet[:nsteps], d_obs, "int")
-    dt = time.perf_counter() - t0
-    Z, X = grid.padded
-    nt_full = int(w.geom.nt[0])
-    per_shot = dt * (nt_full - 1) / (nsteps - 1)
-    return {"value": 1.0 / per_shot, "unit": "shot-gradients/s", "cores": 1, "kind": "oracle",
-            "gcell_updates_per_s": 3.0 * Z * X * (nsteps - 1) / dt / 1e9,
-            "seconds": dt,
-            "sample": f"1 of {w.geom.nshot} shots, first {nsteps} of {nt_full} time steps "
-                      f"(FP64 NumPy, single thread), extrapolated linearly to the full record"}
+    oracle.gradient(w.v_start, grid, geom, w.wavelet[:n], d_obs, "int")
+    return time.perf_counter() - t0, n, nt_full
+
+
+def oracle_pool(wname, nworkers, nshot):
+    """The CPU baseline's process pool, started before this process touches
+    the GPU (its workers build the workloads meanwhile)."""
+    import multiprocessing as mp
+    _, avail = host_cpu()
+    P = max(1, min(nworkers or avail, avail, 16, nshot))
+    return mp.get_context("spawn").Pool(P, initializer=_init_oracle_worker, initargs=((wname, "anomaly_200x100"),)), P
+
+
+def cpu_baseline(w, wname, nsteps, pool, P):
+    """The FP64 oracle as it stands, timed on the host's cores: a process
+    pool with one shot of the workload per worker, each over the first
+    `nsteps` time steps (its cost per step is constant: forward sweep with
+    snapshots, segment recomputation and adjoint sweep), extrapolated to the
+    whole record; beside it the 200x100 anomaly workload (one shot, nt 1000)
+    in full on every worker."""
+    model, avail = host_cpu()
+    with pool:
+        pool.map(_oracle_shot_sample, [("anomaly_200x100", 0, 2)] * P, chunksize=1)   # workers up
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_shot_sample, [(wname, s, nsteps) for s in range(P)], chunksize=1)
+        wall = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        small = pool.map(_oracle_shot_sample, [("anomaly_200x100", 0, 1000)] * P, chunksize=1)
+        wall_small = time.perf_counter() - t1
+    Z, X = w.grid.padded
+    shot_fraction = sum((n - 1) / (nt - 1) for _, n, nt in res)
+    cell_steps = sum(3.0 * Z * X * (n - 1) for _, n, _ in res)
+    from paper_1406_1864_amd.synthetic import anomaly_200x100
+    a = anomaly_200x100()
+    Za, Xa = a.grid.padded
+    return {"value": shot_fraction / wall, "unit": "shot-gradients/s", "cores": P, "kind": "oracle",
+            "gcell_updates_per_s": cell_steps / wall / 1e9, "seconds": wall, "cpu_model": model,
+            "cores_available": avail,
+            "sample": f"{P} worker processes, one shot each ({wname} shots 0..{P - 1}), the first "
+                      f"{res[0][1]} of {res[0][2]} time steps of each (FP64 NumPy, one thread per worker), "
+                      f"shot-gradients extrapolated linearly to the whole record",
+            "anomaly_200x100_full": {"value": P / wall_small, "unit": "shot-gradients/s", "seconds": wall_small,
+                                     "gcell_updates_per_s": P * 3.0 * Za * Xa * 999 / wall_small / 1e9,
+                                     "sample": f"{P} workers, each the whole 1-shot, nt 1000 gradient"}}
 
 
 def time_extended_image(args, grid, geom, w, d_obs, ex, dev):
@@ -309,6 +391,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path would shard by shots "
               "(a subset per GPU and one all-reduce of g, H1, D and J), which is not implemented", file=sys.stderr)
         sys.exit(2)
+    pool = npool = None
+    if not args.no_cpu:
+        pool, npool = oracle_pool(WNAME[args.workload], args.cpu_workers, 32)
     import torch
     from paper_1406_1864_amd import binding as B
     from paper_1406_1864_amd.autograd import FWIProblem, fwi_misfit
@@ -431,7 +516,7 @@ def main():
     full = (shots == full_shots and not args.nt)
     # the dominant kernel: the one-step or the two-step reverse sweep
     rev_kernel = "k_reverse2" if RS == 2 else "k_reverse"
-    traffic = measured_traffic(rev_kernel, chosen) if (args.workload == "layered" and full) else None
+    traffic = measured_traffic(rev_kernel, chosen, args.workload) if full else None
     nrec_mean = float(np.mean(nrec)) if shots else 0.0
     out = {
         "metric": "shot-gradients/s and Gcell-updates/s (fraction of HBM roofline), batched vs plain",
@@ -505,9 +590,9 @@ def main():
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded
-        # about 15 s: the oracle's gradient costs ~35 ns per padded cell and step on one core
+        # about 15 s per worker: the oracle's gradient costs ~35 ns per padded cell and step on one core
         nsteps = args.cpu_steps or int(np.clip(15.0 / (Zc * Xc * 3.5e-8), 50, int(w.geom.nt[0])))
-        out["cpu_baseline"] = cpu_baseline(w, nsteps)
+        out["cpu_baseline"] = cpu_baseline(w, WNAME[args.workload], nsteps, pool, npool)
     print(json.dumps(out), flush=True)
 
 
