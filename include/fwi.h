@@ -33,10 +33,8 @@
  *     HIP device memory on the current device.  Geometry arrays inside
  *     fwi_geometry are HOST pointers; they are read during the call only.
  *   - The library never allocates device memory: all scratch lives in the
- *     caller's workspace, sized by fwi_workspace_bytes().  One exception:
- *     fwi_offset_diag_exact runs its DFT GEMMs through rocBLAS, whose
- *     per-device handle (created on the first call) manages its own device
- *     memory and may allocate on a call with new GEMM shapes.
+ *     caller's workspace, sized by fwi_workspace_bytes() (for
+ *     fwi_offset_diag_exact by fwi_offset_diag_exact_workspace_bytes()).
  *   - Calls are asynchronous on `hip_stream` (a hipStream_t, NULL = default
  *     stream).  Do not run two calls concurrently on the same workspace.
  *   - Return 0 on success or a negative FWI_ERR_* code.  Every host-side check
@@ -332,15 +330,19 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  * forward run per receiver and per shot, shots_in_flight runs at a time
  * (default 4; of exec only shots_in_flight, tile_rows and prefetch are used:
  * the sweeps are direct one-step launches, not graphs, and not autotuned).
- * A run's series are captured 8192 / shots_in_flight updates at a time (a
- * multiple of 64, at least 64) and folded into its spectra by a GEMM with
- * the DFT matrix (rocBLAS), in FP32 (dft = FWI_DFT_FP32) or as three bf16
- * products with FP32 accumulation of the series and the DFT matrix split
- * into bf16 pairs (FWI_DFT_BF16X3: about 16 significant bits per product,
- * the lo*lo term dropped).  The workspace holds the chunks and spectra of
- * the runs in flight: see fwi_offset_diag_exact_workspace_bytes (0 on bad
- * arguments).  Not with a free surface.  diag: device [2 hmax + 1][nz][nx],
- * overwritten. */
+ * A run's series are captured in FP32, 8192 / shots_in_flight updates at a
+ * time (a multiple of 64, at least 64), and folded into its spectra by the
+ * library's matrix-core kernel, the DFT matrix generated on chip from exact
+ * phase tables: in FP32 (dft = FWI_DFT_FP32, v_mfma_f32_16x16x4_f32) or as
+ * three bf16 products with FP32 accumulation of the series and the DFT
+ * matrix split into bf16 pairs (FWI_DFT_BF16X3, v_mfma_f32_16x16x32_bf16:
+ * about 16 significant bits per product, the lo*lo term dropped).  The
+ * powers of a run's spectra are added to its side's sums by the kernel that
+ * folds in its last chunk.  The workspace holds the chunks and spectra of
+ * the runs in flight, the summed powers and the phase tables: see
+ * fwi_offset_diag_exact_workspace_bytes (0 on bad arguments; the same for
+ * both arithmetics).  Not with a free surface.  diag: device
+ * [2 hmax + 1][nz][nx], overwritten. */
 enum { FWI_DFT_FP32 = 0, FWI_DFT_BF16X3 = 1 };
 size_t fwi_offset_diag_exact_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
                                              const fwi_exec *exec, int hmax, double fmax, int dft);

@@ -458,7 +458,7 @@ def hessian_diag(v, wavelet, grid, geom, kind=HESS_EQ1, hmax=0, rcv_model="pm", 
 def offset_diag_exact(v, wavelet, grid, geom, hmax, fmax=0.0, exec_=None, ws=None, device="cuda", dft=None):
     """Offset diagonal with the exact receiver term, D[2 hmax + 1][nz][nx]
     (fmax in Hz bounds the frequency band, 0 keeps every bin; dft selects
-    the DFT GEMM's arithmetic, DFT_BF16X3 by default)."""
+    the arithmetic of the spectra on the matrix cores, DFT_BF16X3 by default)."""
     dft = DFT_BF16X3 if dft is None else dft
     torch = _torch()
     G = _geo(geom)

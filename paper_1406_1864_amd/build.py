@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfwi.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fwi_kernels.hip", "fwi_runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fwi_kernels.hip", "fwi_dft.hip", "fwi_runtime.hip")]
 ARCH = os.environ.get("FWI_OFFLOAD_ARCH", "gfx950")
 
 
@@ -21,9 +21,7 @@ def build(verbose=False):
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            # packed FP32 instructions are kept out of the generated code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I" + os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES + [
-           # the DFT of the exact offset diagonal's series is a plain GEMM
-           "-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocblas"]
+           "-I" + os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -112,15 +112,13 @@ struct StepArgs {
   // Born modelling (forward sweep only): the perturbation wavefield
   float* bu;            // [cs][3][field]  du[n] at level n & 1, its increment at level 2
   const float* bw;      // 2 dv / v on the padded grid (zero outside the model)
-  // series capture (forward sweep, kFwdCapD / kFwdCapU).  The model cells
-  // are cut into blocks of 2^cap_lg; entry e = slot * cap_nblk + block holds
-  // cap_T columns of 2^cap_lg rows, and the value of update n of cell `cell`
-  // goes to element (e * cap_T + n - cap_n0) * 2^cap_lg + (cell & (2^cap_lg
-  // - 1)), as FP32, or (cap_split) as uint16 bf16 values hi, lo, hi at that
-  // element and cap_lo, 2 cap_lo elements further on
-  void* cap;
-  int64_t cap_lo;
-  int32_t cap_n0, cap_split, cap_T, cap_nblk, cap_lg;
+  // series capture (forward sweep, kFwdCapD / kFwdCapU): the value of
+  // update n of model cell `cell` (row-major model index) goes, as FP32, to
+  // element (slot * cap_T + n - cap_n0) * cap_R + cell of cap: per slot a
+  // chunk of cap_T updates, time-major, cap_R >= nz nx cells per row
+  float* cap;
+  int64_t cap_R;
+  int32_t cap_n0, cap_T;
 };
 
 // Extended imaging over one window of reverse launch steps
@@ -213,20 +211,47 @@ hipError_t launch_gradient_out(const Dims& d, const float* gacc, int S, const fl
                                const double* scale, double fac, float* grad, const int32_t* err, hipStream_t s);
 hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const ShotDesc* shots,
                              const int32_t* trace_shot, float* data, hipStream_t s);
-// exact offset diagonal, the DFT matrix of the captured series:
-// w(t, c) = cos / sin (2 pi k t / L) for c = 2k / 2k+1, t < Tn, k < K.
-// Tc = 0: FP32 W[t + c ldw] (rows Tn .. ldw-1 zero).  Tc > 0: for each chunk
-// q of tc = min(Tc, Tn - q Tc) steps, the bf16 matrix [Wh; Wh; Wl] of the
-// chunk's rows (3 tc rows, ld 3 Tc) at element q 2K 3Tc
-hipError_t launch_twiddle(void* W, int Tn, int ldw, int K, int L, int Tc, hipStream_t s);
-// P[k][cell] += sum over nslots of C[e][2k][r]^2 + C[e][2k+1][r]^2 with
-// e = slot nblk + (cell >> lg), r = cell & (2^lg - 1) (ld 2^lg per column)
-hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, int nblk, int lg, float* P,
-                            hipStream_t s);
+// exact offset diagonal: spectra of the captured series on the matrix cores
+// (fwi_dft.hip).  A workgroup owns kDftCols columns of the DFT matrix (the
+// cosine and sine rows of kDftCols / 2 bins) by kDftCells model cells and
+// walks the time steps kDftKT at a time.
+constexpr int kDftCols = 256;
+constexpr int kDftCells = 128;
+constexpr int kDftKT = 32;
+
+struct DftArgs {
+  const float* X;       // captured series [slot][Tc][R], FP32, time-major
+  int64_t R;            // cells per series row: ntile * kDftCells >= model
+  int64_t xslot;        // floats per slot of X (Tc * R)
+  int32_t tc;           // valid steps of this chunk: rows t >= tc count as 0
+  int32_t nslab;        // slabs of kDftKT steps in the chunk: ceil(tc / kDftKT)
+  const float2* Tb;     // [Kp][kDftKT] (cos, sin)(2 pi k tau / L)       (launch_dft_tables)
+  const float2* Ph;     // [slab][Kp]   (cos, sin)(2 pi k 32 slab / L)
+  int32_t Kp;           // bins of the tables: Cp / 2
+  int32_t j0;           // the chunk's first slab (absolute)
+  int32_t Cp;           // columns of the DFT matrix and of C: 2K rounded up to kDftCols
+  float* C;             // running spectra [slot][Cp][R] (not read when first,
+                        // not written when last)
+  int32_t first, last;  // the run's first / last chunk
+  float* P;             // [Kp][R]: last chunk adds C[2k]^2 + C[2k+1]^2 of every slot
+  int32_t K;
+  int64_t model;
+  int32_t nslots;       // runs of the launch (slots 0 .. nslots-1)
+  int32_t ntile;        // cell tiles
+};
+// split: bf16 hi/lo operands (three products, FP32 accumulation); else FP32
+hipError_t launch_dft(const DftArgs& a, int split, hipStream_t s);
+// the phase tables of the DFT matrix w(t, c) = cos / sin (2 pi k t / L),
+// c = 2k / 2k + 1: Tb[k][tau] for tau < kDftKT and Ph[J][k] for the slabs'
+// first steps t = kDftKT J, J < nslab; (cos, sin) with the phase k t mod L
+// reduced exactly in integers, zero for k >= K
+hipError_t launch_dft_tables(float2* Tb, float2* Ph, int nslab, int Kp, int K, int L, hipStream_t s);
 // D[h][z][x] += scale / v^6 sum_k m_k PA[k][z][x+h] PB[k][z][x-h] for |h| <= hmax
-// (both columns in the model), m_0 = 1, m_{K-1} = 1 if nyq, else 2
-hipError_t launch_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
-                                const float* v, float scale, float* D, const int32_t* err, hipStream_t s);
+// (both columns in the model), m_0 = 1, m_{K-1} = 1 if nyq, else 2; bin k
+// of PA / PB starts at element k * ldp
+hipError_t launch_diag_products(const float* PA, const float* PB, int64_t ldp, int K, int nyq, int nz, int nx,
+                                int hmax, const float* v, float scale, float* D, const int32_t* err,
+                                hipStream_t s);
 hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int kind,
                           const float* hdiag, int hmax, float eps, float* out, uint32_t* maxbits,
                           hipStream_t s);

@@ -86,29 +86,6 @@ __device__ __forceinline__ bool map_tile(const Dims& d, int S, int xcd_map, int 
   return slot < S && tile < T;
 }
 
-// bf16 of x, rounded to nearest even (finite x)
-__device__ __forceinline__ uint16_t bf16_bits(float x) {
-  const uint32_t b = __float_as_uint(x);
-  return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-}
-
-// x as FP32, or split into bf16 hi = bf16(x) and lo = bf16(x - hi) (16
-// significant bits between them), stored as hi, lo, hi at elements i,
-// i + cap_lo and i + 2 cap_lo: the chunk's columns of the operand
-// [Xh | Xl | Xh] whose product with [Wh; Wh; Wl] is X W up to the dropped
-// Xl Wl term (within about 2^-16 of the FP32 product)
-__device__ __forceinline__ void capture(const StepArgs& a, int64_t i, float x) {
-  if (a.cap_split) {
-    uint16_t* c = (uint16_t*)a.cap;
-    const uint16_t hi = bf16_bits(x);
-    c[i] = hi;
-    c[i + a.cap_lo] = bf16_bits(x - __uint_as_float((uint32_t)hi << 16));
-    c[i + 2 * a.cap_lo] = hi;
-  } else {
-    ((float*)a.cap)[i] = x;
-  }
-}
-
 __device__ __forceinline__ int step_of(const StepArgs& a) {
   return a.step_ctr ? (*a.step_ctr + a.step) : a.step;
 }
@@ -415,11 +392,8 @@ __global__ __launch_bounds__(256) void k_forward(StepArgs a) {
           const float D = wv_ * lap;
           E[mi] = (n == 0) ? D * D : fmaf(D, D, E[mi]);
         }
-        if ((FLAGS & (kFwdCapD | kFwdCapU)) && mcell) {
-          const int64_t e = (int64_t)slot * a.cap_nblk + (mi >> a.cap_lg);
-          capture(a, ((e * a.cap_T + (n - a.cap_n0)) << a.cap_lg) + (mi & ((1 << a.cap_lg) - 1)),
-                  (FLAGS & kFwdCapD) ? wv_ * lap : out);
-        }
+        if ((FLAGS & (kFwdCapD | kFwdCapU)) && mcell)
+          a.cap[((int64_t)slot * a.cap_T + (n - a.cap_n0)) * a.cap_R + mi] = (FLAGS & kFwdCapD) ? wv_ * lap : out;
         if (FLAGS & kFwdCkpt) {
           const int ri = strip_index(row, col);
           if (ri >= 0) strip[ri] = out;
@@ -1850,83 +1824,15 @@ hipError_t launch_precond(int nz, int nx, const float* v, const float* grad, int
 
 
 // -------------------------------------------------------------------------
-// Offset diagonal with the exact receiver term: the DFT of the captured
-// series is a plain GEMM against W (the host runtime calls the BLAS); these
-// kernels build W, accumulate the power spectra and form the offset sums.
+// Offset diagonal with the exact receiver term: the offset sums of the
+// summed power spectra of the two sides (the spectra themselves come from
+// the matrix-core kernels of fwi_dft.hip).
 // -------------------------------------------------------------------------
-// w(t, c) = cos / sin (2 pi k t / L) for column c = 2k / 2k+1, 0 for t >= Tn
-__device__ __forceinline__ float twiddle(int t, int c, int Tn, int L) {
-  if (t >= Tn) return 0.0f;
-  // the phase k t / L reduced exactly in integers, the angle in double
-  const int64_t r = ((int64_t)(c >> 1) * t) % L;
-  double sn, cs;
-  sincospi(2.0 * (double)r / (double)L, &sn, &cs);
-  return (float)((c & 1) ? sn : cs);
-}
-
-// FP32: W[t + c ldw].  Split (Tc > 0): chunk q of tc = min(Tc, Tn - q Tc)
-// steps is the matrix [Wh; Wh; Wl] of 3 tc rows (ld 3 Tc, rows past 3 tc
-// zero) at element q 2K 3Tc, with Wh = bf16(w), Wl = bf16(w - Wh) of the
-// chunk's rows t = q Tc + j
-__global__ void k_twiddle(void* W, int Tn, int ldw, int K, int L, int Tc) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (Tc <= 0) {
-    if (i >= (int64_t)ldw * 2 * K) return;
-    ((float*)W)[i] = twiddle((int)(i % ldw), (int)(i / ldw), Tn, L);
-    return;
-  }
-  const int nq = (Tn + Tc - 1) / Tc;
-  if (i >= (int64_t)nq * 2 * K * 3 * Tc) return;
-  const int j = (int)(i % (3 * Tc));
-  const int64_t cq = i / (3 * Tc);
-  const int c = (int)(cq % (2 * K)), q = (int)(cq / (2 * K));
-  const int tc = min(Tc, Tn - q * Tc);
-  uint16_t v = 0;
-  if (j < 3 * tc) {
-    const float w = twiddle(q * Tc + j % tc, c, Tn, L);
-    const uint16_t hi = bf16_bits(w);
-    v = (j < 2 * tc) ? hi : bf16_bits(w - __uint_as_float((uint32_t)hi << 16));
-  }
-  ((uint16_t*)W)[i] = v;
-}
-
-hipError_t launch_twiddle(void* W, int Tn, int ldw, int K, int L, int Tc, hipStream_t s) {
-  if (Tn <= 0 || K <= 0) return hipSuccess;
-  if (ldw < Tn) return hipErrorInvalidValue;
-  const int64_t n = Tc > 0 ? (int64_t)((Tn + Tc - 1) / Tc) * 2 * K * 3 * Tc : (int64_t)ldw * 2 * K;
-  hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, Tn, ldw, K, L, Tc);
-  return hipGetLastError();
-}
-
-__global__ void k_power_acc(const float* C, int64_t model, int K, int nslots, int nblk, int lg, float* P) {
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (cell >= model) return;
-  const int64_t mb = (int64_t)1 << lg;
-  const int64_t blk = cell >> lg, r = cell & (mb - 1);
-  float acc = P[(int64_t)k * model + cell];
-  for (int sl = 0; sl < nslots; ++sl) {
-    const float* c = C + (((int64_t)sl * nblk + blk) * 2 * K + 2 * k) * mb + r;
-    const float re = c[0], im = c[mb];
-    acc = fmaf(re, re, fmaf(im, im, acc));
-  }
-  P[(int64_t)k * model + cell] = acc;
-}
-
-hipError_t launch_power_acc(const float* C, int64_t model, int K, int nslots, int nblk, int lg, float* P,
-                            hipStream_t s) {
-  if (model <= 0 || K <= 0 || nslots <= 0) return hipSuccess;
-  if (((int64_t)nblk << lg) < model) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_power_acc, dim3((unsigned)((model + 255) / 256), (unsigned)K), dim3(256), 0, s, C, model, K,
-                     nslots, nblk, lg, P);
-  return hipGetLastError();
-}
-
 // one thread per model cell, the 2 HM + 1 offset sums in registers (offsets
 // above hmax are skipped); PA is read at x + h, PB at x - h along the row
 template <int HM>
-__global__ void k_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
-                                const float* v, float scale, float* D, const int32_t* err) {
+__global__ void k_diag_products(const float* PA, const float* PB, int64_t ldp, int K, int nyq, int nz, int nx,
+                                int hmax, const float* v, float scale, float* D, const int32_t* err) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.y;
   if (x >= nx || *err) return;
   const int64_t model = (int64_t)nz * nx;
@@ -1936,8 +1842,8 @@ __global__ void k_diag_products(const float* PA, const float* PB, int K, int nyq
   for (int j = 0; j < 2 * HM + 1; ++j) acc[j] = 0.0f;
   for (int k = 0; k < K; ++k) {
     const float mk = (k == 0 || (nyq && k == K - 1)) ? 1.0f : 2.0f;
-    const float* pa = PA + k * model + row;
-    const float* pb = PB + k * model + row;
+    const float* pa = PA + k * ldp + row;
+    const float* pb = PB + k * ldp + row;
 #pragma unroll
     for (int j = 0; j < 2 * HM + 1; ++j) {
       const int h = j - HM;
@@ -1957,18 +1863,24 @@ __global__ void k_diag_products(const float* PA, const float* PB, int K, int nyq
   }
 }
 
-hipError_t launch_diag_products(const float* PA, const float* PB, int K, int nyq, int nz, int nx, int hmax,
-                                const float* v, float scale, float* D, const int32_t* err, hipStream_t s) {
+hipError_t launch_diag_products(const float* PA, const float* PB, int64_t ldp, int K, int nyq, int nz, int nx,
+                                int hmax, const float* v, float scale, float* D, const int32_t* err,
+                                hipStream_t s) {
   if (nz <= 0 || nx <= 0) return hipSuccess;
+  if (ldp < (int64_t)nz * nx) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((nx + 127) / 128), (unsigned)nz), block(128);
   if (hmax <= 4)
-    hipLaunchKernelGGL(k_diag_products<4>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+    hipLaunchKernelGGL(k_diag_products<4>, grid, block, 0, s, PA, PB, ldp, K, nyq, nz, nx, hmax, v, scale, D,
+                       err);
   else if (hmax <= 8)
-    hipLaunchKernelGGL(k_diag_products<8>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+    hipLaunchKernelGGL(k_diag_products<8>, grid, block, 0, s, PA, PB, ldp, K, nyq, nz, nx, hmax, v, scale, D,
+                       err);
   else if (hmax <= 16)
-    hipLaunchKernelGGL(k_diag_products<16>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+    hipLaunchKernelGGL(k_diag_products<16>, grid, block, 0, s, PA, PB, ldp, K, nyq, nz, nx, hmax, v, scale, D,
+                       err);
   else if (hmax <= 32)
-    hipLaunchKernelGGL(k_diag_products<32>, grid, block, 0, s, PA, PB, K, nyq, nz, nx, hmax, v, scale, D, err);
+    hipLaunchKernelGGL(k_diag_products<32>, grid, block, 0, s, PA, PB, ldp, K, nyq, nz, nx, hmax, v, scale, D,
+                       err);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

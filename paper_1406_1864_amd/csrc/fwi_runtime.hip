@@ -11,7 +11,6 @@
 // those inputs; captured graphs are cached inside their plan, keyed by the
 // device pointers they bake in.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1177,38 +1176,21 @@ struct DxGroup {
 struct DxLayout {
   int S = 0;              // series in flight
   size_t plan = 0;        // plan region (offset 0)
-  size_t cap = 0, C = 0, PA = 0, PB = 0, W = 0, imp = 0, wav = 0, total = 0;
+  size_t cap = 0, C = 0, PA = 0, PB = 0, W = 0, imp = 0, wav = 0, total = 0;  // W: the phase tables
   int Tn = 0, K = 0;      // largest series length and bin count
-  int Tc = 0;             // time steps captured between two GEMMs
-  int lg = 0, nblk = 0;   // GEMM row blocks of 2^lg model cells
+  int Tc = 0;             // time steps captured between two DFT launches (a multiple of kDftKT)
+  int Cp = 0;             // columns of the DFT matrix: 2K rounded up to kDftCols
+  int ntile = 0;          // cell tiles of kDftCells model cells
+  int64_t R = 0;          // cells per captured row: ntile * kDftCells
 };
 
 // Run-steps held by the chunk buffer: S runs in flight capture Tc = 8192 / S
 // updates (a multiple of 64) per chunk, so that fewer runs in flight buy
 // longer chunks and fewer read-modify-write passes over the spectra
 constexpr int kDxRunSteps = 8192;
-// default runs in flight: at 2048x768, nt 8000, 4 runs with 2048-update
-// chunks took 138 ms per run (bf16 split), 2 / 3 / 8 / 16 runs 187 / 158 /
-// 156 / 171 ms: fewer runs starve the sweeps, more shorten the chunks
+// default runs in flight (the forward sweeps of fewer runs leave the GPU
+// underused; more runs shorten the chunks)
 constexpr int kDxRuns = 4;
-
-// The GEMMs take blocks of at most 2^16 model cells as batch entries, so
-// that every operand offset inside one entry stays far below 2^31 elements
-// whatever the grid, chunk and band (the library indexes within a matrix in
-// 32 bits)
-constexpr int kDxBlockLog2 = 16;
-
-void dx_blocks(int64_t model, int& lg, int& nblk) {
-  lg = 0;
-  while (lg < kDxBlockLog2 && ((int64_t)1 << lg) < model) ++lg;
-  nblk = (int)((model + ((int64_t)1 << lg) - 1) >> lg);
-}
-
-// leading dimension of the DFT matrix: whole 256-byte lines per column, so
-// that the GEMM's loads of it stay aligned
-int dx_ldw(int Tn) { return (Tn + 63) / 64 * 64; }
-
-size_t dx_sample_bytes(int dft) { return dft == FWI_DFT_FP32 ? 4 : 6; }
 
 void dx_bins(int nt, double dt, double fmax, int& L, int& K, int& nyq) {
   L = 2 * nt;
@@ -1298,7 +1280,8 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
   for (const DxGroup& gr : dx_groups(g, geo)) {
     int L, K, nyq;
     dx_bins(gr.nt, g->dt, fmax, L, K, nyq);
-    // the power kernel takes the bins as its grid's second dimension
+    // a bound on the size of the spectra (K model cells per side), which a
+    // band limit keeps small
     if (K > 65535) return fail(FWI_ERR_ARG, "more than 65535 frequency bins: bound the band with fmax");
     o.Tn = std::max(o.Tn, gr.nt - 1);
     o.K = std::max(o.K, K);
@@ -1312,44 +1295,24 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
     }
   }
   o.S = Smax;
-  o.Tc = std::max(1, std::min(o.Tn, std::max(64, kDxRunSteps / Smax / 64 * 64)));
-  dx_blocks(model, o.lg, o.nblk);
-  const size_t rows = (size_t)o.nblk << o.lg;  // model cells padded to whole blocks
+  const int Tn32 = (o.Tn + kDftKT - 1) / kDftKT * kDftKT;
+  o.Tc = std::max(kDftKT, std::min(Tn32, std::max(64, kDxRunSteps / Smax / 64 * 64)));
+  o.Cp = (2 * o.K + kDftCols - 1) / kDftCols * kDftCols;
+  o.ntile = (int)((model + kDftCells - 1) / kDftCells);
+  o.R = (int64_t)o.ntile * kDftCells;
   size_t off = align_up(o.plan);
   auto take = [&](size_t& field, size_t bytes) {
     field = off;
     off = align_up(off + bytes);
   };
-  // the chunk of 4 (FP32) or 6 (bf16 hi, lo, hi) bytes per sample
-  take(o.cap, dx_sample_bytes(dft) * (size_t)Smax * o.Tc * rows);
-  take(o.C, sizeof(float) * (size_t)Smax * 2 * o.K * rows);
-  take(o.PA, sizeof(float) * (size_t)o.K * model);
-  take(o.PB, sizeof(float) * (size_t)o.K * model);
-  const int nq = (o.Tn + o.Tc - 1) / o.Tc;
-  take(o.W, dft == FWI_DFT_FP32 ? sizeof(float) * (size_t)dx_ldw(o.Tn) * 2 * o.K
-                                : sizeof(uint16_t) * (size_t)nq * 2 * o.K * 3 * o.Tc);
+  take(o.cap, sizeof(float) * (size_t)Smax * o.Tc * o.R);    // the chunk's series (FP32)
+  take(o.C, sizeof(float) * (size_t)Smax * o.Cp * o.R);      // running spectra
+  take(o.PA, sizeof(float) * (size_t)(o.Cp / 2) * o.R);      // summed powers, padded bins x cells
+  take(o.PB, sizeof(float) * (size_t)(o.Cp / 2) * o.R);
+  take(o.W, sizeof(float2) * (size_t)(o.Cp / 2) * (kDftKT + Tn32 / kDftKT));  // phase tables
   take(o.imp, sizeof(float) * (size_t)g->nt_max);
   take(o.wav, sizeof(float) * (size_t)nshot_max * g->nt_max);
   o.total = off;
-  return FWI_OK;
-}
-
-// Per device rocBLAS handles; g_dx_mutex is held while a call sets its
-// handle's stream and enqueues its work.
-std::mutex g_dx_mutex;
-std::map<int, rocblas_handle> g_dx_blas;
-
-int dx_blas(hipStream_t s, rocblas_handle* out) {
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  auto it = g_dx_blas.find(dev);
-  if (it == g_dx_blas.end()) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_create_handle failed");
-    it = g_dx_blas.emplace(dev, h).first;
-  }
-  if (rocblas_set_stream(it->second, s) != rocblas_status_success) return fail(FWI_ERR_HIP, "rocblas_set_stream failed");
-  *out = it->second;
   return FWI_OK;
 }
 
@@ -1709,59 +1672,31 @@ int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const 
   hipStream_t s = (hipStream_t)hip_stream;
   const int nz = grid->nz, nx = grid->nx;
   const int64_t model = (int64_t)nz * nx;
-  const bool split = dft == FWI_DFT_BF16X3;
+  const int split = dft == FWI_DFT_BF16X3;
   HIP_TRY(launch_fill(diag, sizeof(float) * model * (2 * hmax + 1), s));
   const std::vector<DxGroup> groups = dx_groups(grid, geom);
   if (groups.empty()) return FWI_OK;
-  std::lock_guard<std::mutex> lock(g_dx_mutex);
-  rocblas_handle blas = nullptr;
-  if ((rc = dx_blas(s, &blas))) return rc;
-  void* cap = at<char>(workspace, o.cap);
+  float* cap = at<float>(workspace, o.cap);
   float* C = at<float>(workspace, o.C);
   float* PA = at<float>(workspace, o.PA);
   float* PB = at<float>(workspace, o.PB);
-  void* W = at<char>(workspace, o.W);
+  float2* Tb = at<float2>(workspace, o.W);
   float* imp = at<float>(workspace, o.imp);
   float* wav = at<float>(workspace, o.wav);
   // the impulse [1, 0, 0, ...] that starts a receiver's response
   HIP_TRY(launch_fill(imp, sizeof(float) * grid->nt_max, s));
   HIP_TRY(launch_set((int32_t*)imp, 0x3f800000, s));
   const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : kDxRuns;
-  // C[e] (+)= X[e] . Wq for chunk q (updates k0 .. k0+tc-1) and every entry
-  // e (slot, block of mb cells): FP32, X the chunk's series (mb x tc, ld mb)
-  // and Wq rows k0 .. of the DFT matrix (ld ldw); split, [Xh | Xl | Xh]
-  // (mb x 3tc) and the chunk's [Wh; Wh; Wl] (ld 3 Tc), one bf16 GEMM with
-  // FP32 accumulation.  C[e] is mb x 2K (ld mb).
-  const int mb = 1 << o.lg;
-  auto gemm = [&](int ldw, int K, int q, int k0, int tc, int nact) -> int {
-    const float one = 1.0f, beta0 = k0 > 0 ? 1.0f : 0.0f;
-    const int batch = nact * o.nblk;
-    const rocblas_stride sc = (rocblas_stride)2 * K * mb;
-    rocblas_status bs;
-    if (!split) {
-      bs = rocblas_sgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, mb, 2 * K, tc, &one,
-                                         (const float*)cap, mb, (rocblas_stride)o.Tc * mb, (const float*)W + k0,
-                                         ldw, 0, &beta0, C, mb, sc, batch);
-    } else {
-      const uint16_t* wq = (const uint16_t*)W + (int64_t)q * 2 * K * 3 * o.Tc;
-      bs = rocblas_gemm_strided_batched_ex(
-          blas, rocblas_operation_none, rocblas_operation_none, mb, 2 * K, 3 * tc, &one, cap, rocblas_datatype_bf16_r,
-          mb, (rocblas_stride)3 * o.Tc * mb, wq, rocblas_datatype_bf16_r, 3 * o.Tc, 0, &beta0, C,
-          rocblas_datatype_f32_r, mb, sc, C, rocblas_datatype_f32_r, mb, sc, batch, rocblas_datatype_f32_r,
-          rocblas_gemm_algo_standard, 0, 0);
-    }
-    if (bs != rocblas_status_success)
-      return fail(FWI_ERR_HIP, std::string("rocBLAS GEMM of the DFT: ") + rocblas_status_to_string(bs));
-    return FWI_OK;
-  };
   for (const DxGroup& gr : groups) {
     const int Tn = gr.nt - 1;
     int L, K, nyq;
     dx_bins(gr.nt, grid->dt, fmax, L, K, nyq);
-    const int ldw = dx_ldw(Tn);
-    HIP_TRY(launch_twiddle(W, Tn, ldw, K, L, split ? o.Tc : 0, s));
-    HIP_TRY(launch_fill(PA, sizeof(float) * (size_t)K * model, s));
-    HIP_TRY(launch_fill(PB, sizeof(float) * (size_t)K * model, s));
+    const int nslab_all = (Tn + kDftKT - 1) / kDftKT;
+    const int Cp = (2 * K + kDftCols - 1) / kDftCols * kDftCols;
+    float2* Ph = Tb + (size_t)(Cp / 2) * kDftKT;
+    HIP_TRY(launch_dft_tables(Tb, Ph, nslab_all, Cp / 2, K, L, s));
+    HIP_TRY(launch_fill(PA, sizeof(float) * (size_t)(Cp / 2) * o.R, s));
+    HIP_TRY(launch_fill(PB, sizeof(float) * (size_t)(Cp / 2) * o.R, s));
     // the group's shots' wavelets, gathered in group order
     const float* wsrc = wavelet;
     int64_t wst = 0;
@@ -1789,31 +1724,46 @@ int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const 
         HIP_TRY(launch_fill_slots(at<float>(workspace, p->L.u), p->ulevels * p->d.field,
                                   p->ulevels * p->d.field + p->d.guard, slots, p->S, 1, s));
         StepArgs a = step_args(*p, workspace, b, kPhaseFwd, rcv ? imp : wsrc, rcv ? 0 : wst, false);
-        a.cap_T = (split ? 3 : 1) * o.Tc;  // columns per entry
-        a.cap_nblk = o.nblk;
-        a.cap_lg = o.lg;
-        a.cap_split = split;
-        // the series in chunks of Tc updates, each folded into the spectra
-        // (on one stream: forward sweeps run beside a GEMM slowed both)
         a.cap = cap;
-        for (int k0 = 0, c = 0; k0 < Tn; k0 += o.Tc, ++c) {
+        a.cap_T = o.Tc;
+        a.cap_R = o.R;
+        // the series in chunks of Tc updates, each folded into the spectra by
+        // the matrix cores; the run's last chunk adds the powers to its side
+        for (int k0 = 0; k0 < Tn; k0 += o.Tc) {
           const int tc = std::min(o.Tc, Tn - k0);
           a.cap_n0 = k0;
-          a.cap_lo = (int64_t)tc * mb;  // the chunk's three column blocks
           for (int k = k0; k < k0 + tc; ++k) {
             a.step = k;
             HIP_TRY(launch_forward(a, flags, p->pf_fwd, s));
           }
-          if ((rc = gemm(ldw, K, c, k0, tc, nact))) return rc;
+          DftArgs da{};
+          da.X = cap;
+          da.R = o.R;
+          da.xslot = (int64_t)o.Tc * o.R;
+          da.tc = tc;
+          da.nslab = (tc + kDftKT - 1) / kDftKT;
+          da.Tb = Tb;
+          da.Ph = Ph;
+          da.Kp = Cp / 2;
+          da.j0 = k0 / kDftKT;
+          da.Cp = Cp;
+          da.C = C;
+          da.first = k0 == 0;
+          da.last = k0 + tc >= Tn;
+          da.P = rcv ? PB : PA;
+          da.K = K;
+          da.model = model;
+          da.nslots = nact;
+          da.ntile = o.ntile;
+          HIP_TRY(launch_dft(da, split, s));
         }
-        HIP_TRY(launch_power_acc(C, model, K, nact, o.nblk, o.lg, rcv ? PB : PA, s));
       }
     }
     // (4 / v^6) h^4 / (dt^4 L): the source series is D / dt^2, the receiver
     // series h^2 u (the impulse enters as 1 / h^2)
     const double h2 = grid->dx * grid->dx, dt2 = grid->dt * grid->dt;
     const float scale = (float)(4.0 * h2 * h2 / (dt2 * dt2 * L));
-    HIP_TRY(launch_diag_products(PA, PB, K, nyq, nz, nx, hmax, v, scale, diag, err, s));
+    HIP_TRY(launch_diag_products(PA, PB, o.R, K, nyq, nz, nx, hmax, v, scale, diag, err, s));
   }
   return FWI_OK;
 }

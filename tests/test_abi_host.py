@@ -203,12 +203,14 @@ def test_offset_diag_exact_sizing_and_rejects(lib):
     """The exact offset diagonal's workspace grows with the band and the runs
     in flight; bad offsets, a negative band, a free surface, a missing output
     and a short workspace are rejected before any HIP call."""
-    g, geo = _tiny()
+    w = tiny_24x16(nt=300)      # 301 bins: three 256-column tiles of the DFT matrix; 40 Hz: 25 bins, one tile
+    g, geo = w.grid, w.geom
     full = B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0)
     band = B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 40.0)
     one = B.fwi_offset_diag_exact_workspace_bytes(g, geo, B.make_exec(shots_in_flight=1), 4, 0.0)
     assert 0 < band < full and 0 < one < full
-    assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0, B.DFT_BF16X3) > full   # 6 B per sample
+    # both arithmetics capture FP32 series (the split happens on their way into LDS)
+    assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, 4, 0.0, B.DFT_BF16X3) == full
     for hmax, fmax, dft in ((33, 0.0, 0), (-1, 0.0, 0), (24, 0.0, 0), (4, -1.0, 0), (4, float("nan"), 0),
                             (4, 0.0, 2)):
         assert B.fwi_offset_diag_exact_workspace_bytes(g, geo, None, hmax, fmax, dft) == 0, (hmax, fmax, dft)

@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 from paper_1406_1864_amd import binding as B
-from paper_1406_1864_amd.synthetic import Geometry, Grid, anomaly_200x100, offset_2048x768, tiny_24x16
+from paper_1406_1864_amd.synthetic import (Geometry, Grid, anomaly_200x100, gaussian_anomaly, offset_2048x768,
+                                           ricker, tiny_24x16)
 
 from helpers import GRAD_TOL, rel, report
 from test_gpu_parity import cpu, ragged_geometry
@@ -84,6 +85,43 @@ def test_offset_diag_exact_ragged(sif, dft):
     ref = oracle.offset_diag_spectral(v, grid, geom, wav, hmax)
     got = B.offset_diag_exact(v, wav, grid, geom, hmax, 0.0, B.make_exec(shots_in_flight=sif), dft=DFTS[dft])
     check(f"ragged sif={sif} {dft}", ref, got, hmax)
+
+
+@pytest.mark.parametrize("dft", list(DFTS))
+def test_offset_diag_exact_several_chunks_and_column_tiles(dft):
+    """66 receivers in one group with 64 runs in flight: the series are
+    captured 8192 / 64 = 128 updates at a time, so the 299 updates of a
+    300-sample record take three chunks (spectra carried across chunks, a
+    short last chunk of 43 updates ending in a partial slab of 32 steps); the
+    receiver side runs a full batch of 64 and a batch of 2; every bin (301,
+    three 256-column tiles of the DFT matrix, the last one part-empty)."""
+    w = tiny_24x16(nt=300)
+    rec = [(z, x) for z in (1, 5, 9) for x in range(1, 23)]
+    n = len(rec)
+    geom = Geometry(np.array([1, 1], np.int32), np.array([3, 20], np.int32), np.array([0, n, 2 * n], np.int32),
+                    np.array([r[0] for r in rec] * 2, np.int32), np.array([r[1] for r in rec] * 2, np.int32),
+                    np.array([300, 300], np.int32))
+    hmax = 4
+    ref = oracle.offset_diag_spectral(w.v_start, w.grid, geom, w.wavelet, hmax)
+    got = B.offset_diag_exact(w.v_start, w.wavelet, w.grid, geom, hmax, 0.0, B.make_exec(shots_in_flight=64),
+                              dft=DFTS[dft])
+    check(f"66 receivers, 64 runs in flight, 3 chunks, {dft}", ref, got, hmax)
+
+
+@pytest.mark.parametrize("dft", list(DFTS))
+def test_offset_diag_exact_many_cell_tiles(dft):
+    """A 300x50 model (15000 cells: 117 tiles of 128 cells and a partial
+    one), nt 400, one shot and three receivers, band to 40 Hz, |h| <= 6."""
+    nz, nx = 50, 300
+    grid = Grid(nz, nx, 10.0, 1e-3, 400, 10, 2300.0)
+    v = gaussian_anomaly(nz, nx, 2000.0, 0.1, 6.0, iz0=25, ix0=150)
+    geom = Geometry(np.array([1], np.int32), np.array([100], np.int32), np.array([0, 3], np.int32),
+                    np.array([1, 1, 2], np.int32), np.array([20, 150, 280], np.int32), np.array([400], np.int32))
+    wav = ricker(15.0, 1e-3, 400).astype(np.float32)
+    hmax = 6
+    ref = oracle.offset_diag_spectral(v, grid, geom, wav, hmax, fmax=40.0)
+    got = B.offset_diag_exact(v, wav, grid, geom, hmax, 40.0, B.make_exec(shots_in_flight=2), dft=DFTS[dft])
+    check(f"300x50, 118 cell tiles, {dft}", ref, got, hmax)
 
 
 def test_offset_diag_exact_skips_shots_without_receivers():
