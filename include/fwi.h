@@ -228,6 +228,29 @@ int fwi_gradient(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec 
                  int hmax, int rcv_model, float *offset_diag,
                  void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* fwi_gradient without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same inputs, outputs and results as
+ * fwi_gradient; the scratch lives in a static device array of
+ * FWI_STATIC_SCRATCH_BYTES (64 MiB) per GPU, which the library holds until
+ * the process ends.  The call allocates nothing: it runs direct launches
+ * with the heuristic settings (exec's graph_steps and autotune are ignored,
+ * its other fields apply) and returns FWI_ERR_WORKSPACE, before anything is
+ * enqueued, when the call would need more scratch than the array holds (the
+ * need is fwi_workspace_bytes(grid, geom, exec with graph_steps = -1 and
+ * autotune = 0, FWI_WS_GRADIENT, hmax)).  Every call on one GPU uses that
+ * GPU's one array and leaves its contents behind (each call sets up what it
+ * reads): calls that overlap on one GPU -- on other streams or from other
+ * threads -- race, and the caller must serialise them.  The device check of v
+ * records its flag in that array, which fwi_status cannot read; a
+ * non-finite or over-CFL v leaves the outputs unspecified. */
+#define FWI_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int fwi_gradient_static(const fwi_grid *grid, const fwi_geometry *geom, const fwi_exec *exec,
+                        const float *v, const float *wavelet, int64_t wavelet_stride,
+                        const float *d_obs, int misfit,
+                        double *J, float *grad, float *illum,
+                        int hmax, int rcv_model, float *offset_diag, void *hip_stream);
+
 /* Offset-extended image: eq. (6) applied to the adjoint-state wavefields,
  * i.e. the gradient of J with respect to the extended model of eq. (5)
  * (section 3), for horizontal subsurface offsets h = -hmax .. hmax cells:

@@ -33,6 +33,7 @@ FWI_ERR_HIP = -5
 FWI_ERR_NONFINITE = -6
 FWI_ERR_STATE = -7
 FWI_CFL_LIMIT = 0.5546324796655889
+FWI_STATIC_SCRATCH_BYTES = 64 << 20   # the static scratch of fwi_gradient_static, per GPU
 
 EXEC_BATCHED, EXEC_PLAIN = 0, 1
 MISFIT_L2, MISFIT_TIME_INTEGRAL = 0, 1
@@ -83,6 +84,9 @@ _SIGS = {
     "fwi_gradient": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p, c_void_p,
                              c_int64, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
                              c_void_p, c_size_t, c_void_p]),
+    "fwi_gradient_static": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
+                                    c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int,
+                                    c_void_p, c_void_p]),
     "fwi_extended_image": (c_int, [POINTER(fwi_grid), POINTER(fwi_geometry), POINTER(fwi_exec), c_void_p,
                                    c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p,
                                    c_void_p, c_size_t, c_void_p]),
@@ -232,6 +236,15 @@ def fwi_gradient(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J
                                       _ptr(wavelet), int(wavelet_stride), _ptr(d_obs), _MISFIT[misfit], _ptr(J),
                                       _ptr(grad), _ptr(illum), int(hmax), _RCV[rcv_model], _ptr(offset_diag),
                                       _ptr(workspace), int(ws_bytes), _stream(stream)))
+
+
+def fwi_gradient_static(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J, grad, illum, hmax,
+                        rcv_model, offset_diag, stream=None):
+    g, G = make_grid(grid), _geo(geom)
+    return _check(load().fwi_gradient_static(ctypes.byref(g), ctypes.byref(G.struct), _ex(exec_), _ptr(v),
+                                             _ptr(wavelet), int(wavelet_stride), _ptr(d_obs), _MISFIT[misfit],
+                                             _ptr(J), _ptr(grad), _ptr(illum), int(hmax), _RCV[rcv_model],
+                                             _ptr(offset_diag), _stream(stream)))
 
 
 def fwi_extended_image(grid, geom, exec_, v, wavelet, wavelet_stride, d_obs, misfit, J, grad, hmax, image,

@@ -1316,6 +1316,30 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
   return FWI_OK;
 }
 
+// Scratch of fwi_gradient_static: one array per GPU, held until the process
+// ends.  Host code never uses the array's name as an address: the device
+// address of each GPU's copy is looked up once per device, with that device
+// current, and kept.
+__device__ __align__(256) unsigned char scratch[FWI_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;
+
+int static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FWI_ERR_HIP, std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return FWI_OK;
+}
+
 }  // namespace
 }  // namespace fwi
 
@@ -1585,6 +1609,30 @@ int fwi_gradient(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec*
                  size_t ws_bytes, void* hip_stream) {
   return gradient_impl(grid, geom, exec, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, illum,
                        hmax, rcv_model, offset_diag, workspace, ws_bytes, (hipStream_t)hip_stream, 0);
+}
+
+int fwi_gradient_static(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,
+                        const float* wavelet, int64_t wavelet_stride, const float* d_obs, int misfit, double* J,
+                        float* grad, float* illum, int hmax, int rcv_model, float* offset_diag, void* hip_stream) {
+  if (int rc = check_inputs(grid, geom)) return rc;
+  if (int rc = check_exec(exec)) return rc;
+  if (int rc = check_outputs_hess(hmax, rcv_model, offset_diag, grid)) return rc;
+  // direct launches, heuristic settings: no graph is instantiated and no
+  // candidate is timed
+  fwi_exec ex{};
+  if (exec) ex = *exec;
+  ex.graph_steps = -1;
+  ex.autotune = 0;
+  const size_t need = fwi_workspace_bytes(grid, geom, &ex, FWI_WS_GRADIENT, hmax);
+  if (need == 0) return FWI_ERR_ARG;  // sizing failed (message set)
+  if (need > FWI_STATIC_SCRATCH_BYTES)
+    return fail(FWI_ERR_WORKSPACE, "fwi_gradient_static: the call needs " + std::to_string(need) +
+                                       " bytes of scratch, the static array holds " +
+                                       std::to_string((size_t)FWI_STATIC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  if (int rc = static_scratch(&ws)) return rc;
+  return gradient_impl(grid, geom, &ex, v, wavelet, wavelet_stride, d_obs, misfit, J, nullptr, grad, illum, hmax,
+                       rcv_model, offset_diag, ws, FWI_STATIC_SCRATCH_BYTES, (hipStream_t)hip_stream, 0);
 }
 
 int fwi_extended_image(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exec* exec, const float* v,

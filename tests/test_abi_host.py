@@ -246,3 +246,26 @@ def test_offset_diag_exact_fits_an_mi355x_at_full_size(lib):
         for dft in (B.DFT_FP32, B.DFT_BF16X3):
             n = B.fwi_offset_diag_exact_workspace_bytes(w.grid, w.geom, ex, 16, 60.0, dft)
             assert 0 < n < 150e9, (dft, n)
+
+
+def test_gradient_static_rejects_before_any_hip_call(lib):
+    """fwi_gradient_static checks its inputs and its scratch need on the host:
+    bad geometry, a bad hmax and a call that needs more than the static
+    array's FWI_STATIC_SCRATCH_BYTES are refused before anything touches the
+    GPU (here there is none)."""
+    fake = 0x1000
+    w = layered_1024x384(nshot=4)
+    need = B.fwi_workspace_bytes(w.grid, w.geom, B.make_exec(graph_steps=-1), B.WS_GRADIENT, 0)
+    assert need > B.FWI_STATIC_SCRATCH_BYTES
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_gradient_static(w.grid, w.geom, None, fake, fake, 0, fake, "int", fake, fake, None, 0, "pm", None,
+                              stream=0)
+    assert e.value.code == B.FWI_ERR_WORKSPACE
+    g, geo = _tiny()
+    bad = Geometry(geo.src_iz, geo.src_ix, geo.rec_ptr, geo.rec_iz, geo.rec_ix + 100, geo.nt)
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_gradient_static(g, bad, None, fake, fake, 0, fake, "int", fake, fake, None, 0, "pm", None, stream=0)
+    assert e.value.code == B.FWI_ERR_GEOM
+    with pytest.raises(B.FwiError) as e:
+        B.fwi_gradient_static(g, geo, None, fake, fake, 0, fake, "int", fake, fake, None, 40, "pm", fake, stream=0)
+    assert e.value.code == B.FWI_ERR_ARG
