@@ -287,7 +287,7 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     (the untimed first call only with --warmup > 0).  Each run (a
     receiver's impulse response or a shot) is a forward sweep that captures
     the model cells' series 8192 / runs-in-flight updates at a time, each
-    chunk folded into the run's spectra by a GEMM with the DFT matrix."""
+    chunk folded into the run's spectra on the matrix cores (k_dft)."""
     import torch
     from paper_1406_1864_amd import binding as B
     from paper_1406_1864_amd.synthetic import Geometry
@@ -305,12 +305,12 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
     K = min(L // 2 + 1, int(np.floor(fmax * L * grid.dt + 1e-9)) + 1)
     model = grid.nz * grid.nx
     Z, X = grid.padded
-    gemm_flop = 2.0 * model * (nt - 1) * 2 * K          # per run, FP32-equivalent
+    dft_flop = 2.0 * model * (nt - 1) * 2 * K           # per run, FP32-equivalent
     chunk = min(nt - 1, max(64, 8192 // min(args.exact_sif, runs) // 64 * 64))
     full_runs = full_shots + (b - a)
-    out = {"unit": "runs/s (forward sweep with series capture + DFT GEMM)", "shots": ns,
+    out = {"unit": "runs/s (forward sweep with series capture + DFT on the matrix cores)", "shots": ns,
            "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": args.exact_sif, "chunk": chunk,
-           "gemm_shape_per_run": [model, 2 * K, nt - 1], "gemm_tflop_per_run": gemm_flop / 1e12,
+           "dft_shape_per_run": [model, 2 * K, nt - 1], "dft_tflop_per_run": dft_flop / 1e12,
            "cell_updates_per_run": float(Z * X * (nt - 1)), "full_problem_runs": full_runs}
     Dref = D = None
     modes = [m for m in (("fp32", B.DFT_FP32), ("bf16x3", B.DFT_BF16X3)) if args.exact_dft in ("both", m[0])]
@@ -590,8 +590,9 @@ def main():
 
     if not args.no_cpu:
         Zc, Xc = w.grid.padded
-        # about 15 s per worker: the oracle's gradient costs ~35 ns per padded cell and step on one core
-        nsteps = args.cpu_steps or int(np.clip(15.0 / (Zc * Xc * 3.5e-8), 50, int(w.geom.nt[0])))
+        # about 15 s per worker: with one worker per core the oracle's gradient costs ~110 ns per
+        # padded cell and step (~35 ns on a lone core: the workers share the memory bandwidth)
+        nsteps = args.cpu_steps or int(np.clip(15.0 / (Zc * Xc * 1.1e-7), 50, int(w.geom.nt[0])))
         out["cpu_baseline"] = cpu_baseline(w, WNAME[args.workload], nsteps, pool, npool)
     print(json.dumps(out), flush=True)
 

@@ -1165,8 +1165,9 @@ int ws_check(const Plan& p, size_t ws_bytes) {
 // Shots are grouped by (record length, receiver set): a group's receiver term
 // sum_r |G_r|^2 is one power spectrum.  Each group runs the receivers'
 // impulse responses and then its shots as batches of forward sweeps that
-// capture the model cells' series; a GEMM with the DFT matrix gives the
-// spectra, whose powers are summed per side; the offset sums follow.
+// capture the model cells' series; the matrix-core kernel k_dft folds them
+// into the spectra chunk by chunk and sums their powers per side; the offset
+// sums follow.
 struct DxGroup {
   int nt = 0;
   std::vector<int> shots;
