@@ -128,9 +128,11 @@ def measured_traffic(kname, chosen, workload):
         return None
     keys = ("graph_steps", "prefetch_reverse", "shots_in_flight_reverse", "tile_rows_reverse",
             "reverse_steps")
-    if any(p["launch_config"].get(k) != chosen.get(k) for k in keys):
-        return None
-    return p.get("bytes_per_launch")
+    # the summary's main run and the other reverse launch settings it measured
+    for run in [p] + p.get("other_reverse_settings", []):
+        if all(run["launch_config"].get(k) == chosen.get(k) for k in keys):
+            return run.get("bytes_per_launch")
+    return None
 
 
 def host_cpu():
