@@ -679,9 +679,12 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
   Col col = make_col(d, xs0, lane);
   const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
   // only the outer wavefronts load halo columns (wave 0 lanes 0..3 the left,
-  // the last wave lanes 4..7 the right one); the others load their own column
+  // the last wave lanes 4..7 the right one)
   const bool hl_lane = (wv == 0 && lane < 4) || (wv == kWavesPerBlock - 1 && lane >= 4 && lane < 8);
-  col.hsafe = hl_lane ? col.hcol : col.xs;
+  // lanes without a halo column load lane 0's (wave 0 and the inner ones) or
+  // lane 4's (last wave) halo address, one line per wavefront; their value is
+  // overwritten by the lane's own column in the LDS row
+  col.hsafe = hl_lane ? col.hcol : (wv == kWavesPerBlock - 1 ? xs0 + kWave : xs0 - kRadius);
   const int cidx = kRadius + kWave * wv + lane;  // this lane's slot in the workgroup rows
   const int hidx = hl_lane ? (lane < 4 ? lane : kWavesPerBlock * kWave + lane) : cidx;
   const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);  // B's (owned) rows
@@ -821,7 +824,7 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
 #pragma unroll
   for (int j = 0; j < PF; ++j) {
     load_ptA(zA0 + dz * j, uh[j], lh[j], p0[j], pl[j], wr[(j + 4) % W], sa[j]);
-    load_ptB(zA0 - dz * (kRadius - j), gB[j], eB[j], sb[j]);
+    load_ptB(zA0 + dz * kRadius, gB[j], eB[j], sb[j]);  // (B's first row: B starts at position 8)
   }
 
   for (int jb = 0; jb < nA; jb += W) {
@@ -834,7 +837,9 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
       {
         const int qn = (r + PF) % R;
         load_ptA(z + dz * PF, uh[qn], lh[qn], p0[qn], pl[qn], wr[(r + 4 + PF) % W], sa[qn]);
-        load_ptB(z - dz * (kRadius - PF), gB[qn], eB[qn], sb[qn]);
+        // B's operands PF positions ahead; before B starts, its first row
+        // (the rows above it belong to the neighbouring band)
+        load_ptB(zA0 + dz * (max(j + PF, 2 * kRadius) - kRadius), gB[qn], eB[qn], sb[qn]);
       }
       const int sA = (r + 4) % W;  // ring slot of row z
       const int sB = r % W;        // ring slot of row z - 4
@@ -1019,7 +1024,10 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
   Col col = make_col(d, xs0, lane);
   const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
   const bool hl_lane = (wv == 0 && lane < 4) || (wv == kWavesPerBlock - 1 && lane >= 4 && lane < 8);
-  col.hsafe = hl_lane ? col.hcol : col.xs;
+  // lanes without a halo column load lane 0's (wave 0 and the inner ones) or
+  // lane 4's (last wave) halo address, one line per wavefront; their value is
+  // overwritten by the lane's own column in the LDS row
+  col.hsafe = hl_lane ? col.hcol : (wv == kWavesPerBlock - 1 ? xs0 + kWave : xs0 - kRadius);
   const int cidx = kRadius + kWave * wv + lane;
   const int hidx = hl_lane ? (lane < 4 ? lane : kWavesPerBlock * kWave + lane) : cidx;
   const int z0 = zt * d.TZ, z1 = min(z0 + d.TZ, d.Z);  // B's (owned) rows
