@@ -645,6 +645,18 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, 0);
 }
 
+// Two-step sweeps: the grid's last column block may own fewer than 248
+// columns.  Its workgroup lanes at or past (owned columns + 8) feed nothing
+// it stores (B's owned lanes read A's results up to 4 lanes further, A reads
+// its inputs up to 4 more), so a wavefront made only of such lanes ends
+// before the sweep; the per-row barrier then synchronises the others only
+// (a workgroup barrier counts the wavefronts that have not ended).
+__device__ __forceinline__ bool idle_wave(const Dims& d, int xs0, int wv) {
+  const int blk0 = xs0 - kWave * wv;  // storage column of the workgroup's lane 0
+  const int owned_end = min(kWavesPerBlock * kWave - kRadius, d.off + d.X - blk0);
+  return kWave * wv >= owned_end + 2 * kRadius;
+}
+
 // (at least 4 wavefronts per SIMD: the compiler keeps the deeper prefetch
 // within 128 VGPRs)
 template <int PF, bool EXT>
@@ -676,6 +688,7 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
   const int xt = tile % d.XT, zt = tile / d.XT;  // xt % 4 == wv: the workgroup's columns
   // lane 0's storage column; B owns the workgroup's columns 4 .. 251
   const int xs0 = tile2_x0(d.off, xt);
+  if (idle_wave(d, xs0, wv)) return;
   Col col = make_col(d, xs0, lane);
   const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
   // only the outer wavefronts load halo columns (wave 0 lanes 0..3 the left,
@@ -1021,6 +1034,7 @@ __global__ __launch_bounds__(256, 4) void k_forward2(StepArgs a) {
   const Dims& d = a.d;
   const int xt = tile % d.XT, zt = tile / d.XT;  // xt % 4 == wv
   const int xs0 = tile2_x0(d.off, xt);
+  if (idle_wave(d, xs0, wv)) return;
   Col col = make_col(d, xs0, lane);
   const bool own_col = (wv > 0 || lane >= kRadius) && (wv < kWavesPerBlock - 1 || lane < kWave - kRadius) && col.xin;
   const bool hl_lane = (wv == 0 && lane < 4) || (wv == kWavesPerBlock - 1 && lane >= 4 && lane < 8);
