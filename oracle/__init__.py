@@ -11,4 +11,4 @@ from .acoustic import (C8, CFL_LIMIT, Propagator, laplacian, sponge_gamma, padde
 from .hessian import (aperture_factor, offset_diag, shot_scaling, offset_scaling,
                       precondition, extended_born_columns, offset_diag_exact, extended_image,
                       born_shot, born, gn_hvp, spectral_bins, green_series,
-                      source_series, power, offset_diag_spectral)
+                      source_series, power, offset_diag_spectral, offset_diag_spectral_cells)

@@ -299,6 +299,41 @@ def power(series, L, K):
     return X.real ** 2 + X.imag ** 2
 
 
+def offset_diag_spectral_cells(v, grid, geom, wavelet, cells, fmax=None, shots=None):
+    """``offset_diag_spectral`` at the given cells only: D(x, h) for each
+    (iz, ix, h) of ``cells`` (model indices, x - h and x + h inside the
+    model), from the same series recorded at x + h (the shot's wavefield,
+    ``source_series``) and at x - h (each receiver's unit-impulse wavefield,
+    ``green_series``) instead of kept on the whole grid, so that a full-size
+    grid fits in memory.  Returns an array of len(cells)."""
+    v = np.asarray(v, np.float64)
+    cz = np.array([c[0] for c in cells], np.int64)
+    cx = np.array([c[1] for c in cells], np.int64)
+    ch = np.array([c[2] for c in cells], np.int64)
+    assert np.all(cx - np.abs(ch) >= 0) and np.all(cx + np.abs(ch) < v.shape[1])
+    shots = range(geom.nshot) if shots is None else shots
+    out = np.zeros(len(cells))
+    for s in shots:
+        shot = geom.shot(s)
+        riz, rix, nt = shot[2], shot[3], int(shot[4])
+        L, K, m = spectral_bins(nt, grid.dt, fmax)
+        w = np.asarray(wavelet[s] if np.ndim(wavelet) == 2 else wavelet, np.float64)
+        # source side: u[n] at x + h, n = 0 .. nt-1, behind u[-1] = 0
+        u = forward(v, grid, (shot[0], shot[1], cz, cx + ch, nt), w)
+        up = np.concatenate([np.zeros((len(cells), 1)), u], axis=1)
+        A = (up[:, 2:] - 2.0 * up[:, 1:-1] + up[:, :-2]) / grid.dt ** 2
+        PA = power(A.T, L, K)
+        PB = np.zeros_like(PA)
+        imp = np.zeros(nt)
+        imp[0] = 1.0
+        for r in range(len(riz)):
+            # receiver side: h^2 u[n+1] at x - h of a unit source term at the receiver
+            ur = forward(v, grid, (int(riz[r]), int(rix[r]), cz, cx - ch, nt), imp)
+            PB += power((ur[:, 1:] * grid.dx ** 2).T, L, K)
+        out += np.einsum("k,kc,kc->c", m, PA, PB) / L
+    return out * 4.0 / v[cz, cx] ** 6
+
+
 def offset_diag_spectral(v, grid, geom, wavelet, hmax, fmax=None, shots=None):
     """Diagonal of the subsurface-offset Hessian (section 3, y = x and
     h_bar = h) with the exact receiver term in place of the aperture factor:

@@ -4,12 +4,11 @@ every offset slice to the Hessian-diagonal tolerance (relative L2 1e-3), with
 every bin and with a band limit, over shared and separate receiver sets,
 uneven record lengths, several runs in flight and batches of one.
 
-At the full 2048x768 size the oracle is out of reach; there the diagonal is
-checked at sampled (x, h) against a property of the scheme that holds at any
-size: by reciprocity the receiver series at x - h is the trace at the
-receiver of a unit impulse fired at x - h, and the source series at x + h is
-the second difference of the shot's trace there, so the diagonal at (x, h)
-is the band-limited product of the spectra of two recorded traces."""
+At the full 2048x768 size the diagonal is compared at sampled (x, h) with
+stored values of the oracle's per-cell form (the same series recorded at
+x +- h only)."""
+import pathlib
+
 import numpy as np
 import pytest
 
@@ -23,6 +22,7 @@ from test_gpu_parity import cpu, ragged_geometry
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 
 def check(tag, ref, got, hmax):
@@ -160,55 +160,30 @@ def test_offset_diag_exact_repeated_calls_agree():
     assert torch.equal(a, b)
 
 
-def band_power(x, L, K):
-    """sum over the kept bins of the one-sided DFT: m_k |X_k|^2 / L."""
-    X = np.fft.rfft(np.asarray(x, np.float64), n=L)[:K]
-    m = np.full(K, 2.0)
-    m[0] = 1.0
-    if K == L // 2 + 1:
-        m[-1] = 1.0
-    return m, X.real ** 2 + X.imag ** 2
-
-
 @pytest.mark.parametrize("dft", list(DFTS))
-def test_offset_diag_exact_full_size_reciprocity(dft):
+def test_offset_diag_exact_full_size_against_oracle(dft):
     """2048x768 at dx = 6.25 m (64-cell sponge, nt 8000, dt 0.5 ms, Ricker
     15 Hz, band to 60 Hz), one shot and two of its receivers, offsets up to
-    16 cells: sampled (x, h) against traces of the same engine (property of
-    the scheme: reciprocity and the DFT's definition, no oracle)."""
+    16 cells: sampled (x, h) against the FP64 oracle's values
+    (oracle.offset_diag_spectral_cells, stored by tests/golden/make_golden.py
+    exactdiag_2048x768_cells)."""
+    gold = np.load(GOLDEN / "exactdiag_2048x768_cells.npz")
     w = offset_2048x768(nshot=1)
     grid, g = w.grid, w.geom
-    rec = np.array([100, 900], np.int32)     # receivers at ix 200 and 1800
-    geom = Geometry(g.src_iz, g.src_ix, np.array([0, 2], np.int32), g.rec_iz[rec], g.rec_ix[rec], g.nt)
-    hmax, fmax = 16, 60.0
+    rec = gold["receivers"]
+    geom = Geometry(g.src_iz, g.src_ix, np.array([0, len(rec)], np.int32), g.rec_iz[rec], g.rec_ix[rec], g.nt)
+    hmax = 16
     ex = B.make_exec(shots_in_flight=2)
-    D = cpu(B.offset_diag_exact(w.v_start, w.wavelet, grid, geom, hmax, fmax, ex, dft=DFTS[dft]))
+    D = cpu(B.offset_diag_exact(w.v_start, w.wavelet, grid, geom, hmax, float(gold["fmax"]), ex, dft=DFTS[dft]))
     torch.cuda.empty_cache()
-    nt = int(geom.nt[0])
-    L = 2 * nt
-    K = min(L // 2 + 1, int(np.floor(fmax * L * grid.dt + 1e-9)) + 1)
-    # sampled cells (iz, ix, h): near the source, deep, and both offset signs
-    cells = [(4, 40, 3), (100, 700, 0), (300, 1024, -16), (500, 1500, 16), (700, 300, -7), (767, 2000, 5)]
-    # source side: the shot recorded at every x + h
-    sg = Geometry(g.src_iz, g.src_ix, np.array([0, len(cells)], np.int32),
-                  np.array([c[0] for c in cells], np.int32), np.array([c[1] + c[2] for c in cells], np.int32), g.nt)
-    # traces of duplicate receivers are rejected: the sampled cells differ
-    u = cpu(B.forward(w.v_start, w.wavelet, grid, sg)).astype(np.float64)     # u[n], n = 0 .. nt-1
-    up = np.concatenate([np.zeros((len(cells), 1)), u], axis=1)              # u[-1] .. u[nt-1]
-    A = (up[:, 2:] - 2.0 * up[:, 1:-1] + up[:, :-2]) / grid.dt ** 2             # D[i+1] / dt^2
-    imp = np.zeros(grid.nt_max, np.float32)
-    imp[0] = 1.0
-    for c, (iz, ix, h) in enumerate(cells):
-        # receiver side: a unit impulse at x - h, recorded at both receivers
-        rg = Geometry(np.array([iz], np.int32), np.array([ix - h], np.int32), np.array([0, 2], np.int32),
-                      geom.rec_iz, geom.rec_ix, g.nt)
-        ur = cpu(B.forward(w.v_start, imp, grid, rg)).astype(np.float64)
-        m, PA = band_power(A[c], L, K)
-        want = 0.0
-        for r in range(2):
-            _, PB = band_power(grid.dx ** 2 * ur[r, 1:], L, K)
-            want += float(np.sum(m * PA * PB)) / L
-        want *= 4.0 / float(w.v_start[iz, ix]) ** 6
+    # the cells whose diagonal is within 12 decades of the largest sampled one
+    # (by the stored oracle values): the bottom-right corner, 13 km from the
+    # source, sees only the head of the wave as the record ends (1e-29 of the
+    # near-source value), where FP32 wavefields keep no relative precision
+    # and a relative L2 per offset slice gives such a cell no weight
+    live = gold["D"] >= 1e-12 * gold["D"].max()
+    assert live.sum() >= 5
+    for (iz, ix, h), want in zip(gold["cells"][live], gold["D"][live]):
         got = float(D[h + hmax, iz, ix])
         assert report(f"exact diag 2048x768 {dft} (z {iz}, x {ix}, h {h})", abs(got / want - 1.0), GRAD_TOL) < GRAD_TOL
 

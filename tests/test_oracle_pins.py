@@ -768,6 +768,29 @@ def test_offset_diag_spectral_is_full_response_column_norm():
     assert np.all(D[0, :, :2] == 0) and np.all(D[4, :, -2:] == 0)
 
 
+def test_offset_diag_spectral_cells_matches_whole_grid_form():
+    """The per-cell form (series recorded at x +- h only) against the
+    time-domain column norm of the whole response (no DFT) and against the
+    whole-grid spectral form with a band limit."""
+    grid, v, geom, wav = long_record_case(nt=240, nsponge=8)
+    got = oracle.offset_diag_spectral_cells(v, grid, geom, wav, DIAG_CELLS)
+    ref = np.zeros(len(DIAG_CELLS))
+    for s in range(geom.nshot):
+        shot = geom.shot(s)
+        A = oracle.source_series(v, grid, shot, wav)
+        for r in range(len(shot[2])):
+            B = oracle.green_series(v, grid, int(shot[2][r]), int(shot[3][r]), shot[4])
+            for c, (iz, ix, h) in enumerate(DIAG_CELLS):
+                cc = np.convolve(B[:, iz, ix - h], A[:, iz, ix + h])
+                ref[c] += 4.0 / v[iz, ix] ** 6 * np.sum(cc * cc)
+    assert np.max(np.abs(got / ref - 1.0)) < 1e-10
+    Db = oracle.offset_diag_spectral(v, grid, geom, wav, 2, fmax=40.0)
+    gotb = oracle.offset_diag_spectral_cells(v, grid, geom, wav, DIAG_CELLS, fmax=40.0)
+    want = np.array([Db[h + 2, iz, ix] for iz, ix, h in DIAG_CELLS])
+    assert np.max(np.abs(gotb / want - 1.0)) < 1e-10
+    assert np.max(np.abs(gotb / got - 1.0)) > 1e-6       # the band limit does cut something
+
+
 def test_offset_diag_spectral_matches_jacobian_columns_on_a_long_record():
     """When the response has left the grid before the record ends, the exact
     diagonal diag(J_ext^T J_ext) of the conventional misfit (explicit columns,
