@@ -813,7 +813,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   else TZf = {16, 32, 64, 128};
   if (ex && ex->tile_rows_reverse > 0) TZr = {ex->tile_rows_reverse};
   else if (ex && ex->tile_rows > 0) TZr = {ex->tile_rows};
-  else TZr = {8, 12, 16, 32, 64};
+  else TZr = {8, 12, 16, 24, 32, 64};
   if (ex && ex->prefetch > 0) PFs = {ex->prefetch};
   else PFs = {1, 3, 7};
   if (ex && ex->prefetch_reverse > 0) RFs = {ex->prefetch_reverse};
