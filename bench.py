@@ -69,7 +69,8 @@ def parse():
                     help="DFT arithmetic(s) timed for the exact offset diagonal")
     ap.add_argument("--exec", type=str, default="",
                     help="pin the launch configuration instead of autotuning: "
-                         "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps]")
+                         "S,TZ,graph_steps,prefetch,prefetch_reverse[,S_rev,TZ_rev,reverse_steps,forward_steps"
+                         "[,graph_branches]]")
     return ap.parse_args()
 
 
@@ -127,7 +128,7 @@ def measured_traffic(kname, chosen, workload):
     if p.get("kernel_source_sha") != kernel_hash():
         return None
     keys = ("graph_steps", "prefetch_reverse", "shots_in_flight_reverse", "tile_rows_reverse",
-            "reverse_steps")
+            "reverse_steps", "graph_branches")
     # the summary's main run and the other reverse launch settings it measured
     for run in [p] + p.get("other_reverse_settings", []):
         if all(run["launch_config"].get(k) == chosen.get(k) for k in keys):
@@ -443,9 +444,10 @@ def main():
     if args.exec:
         vals = [int(x) for x in args.exec.split(",")]
         S_, TZ_, G_, PF_, PR_ = vals[:5]
-        SR_, TZR_, RS_, FS_ = (vals[5:9] + [0, 0, 0, 0])[:4]
+        SR_, TZR_, RS_, FS_, GB_ = (vals[5:10] + [0, 0, 0, 0, 0])[:5]
         ex = B.make_exec(shots_in_flight=S_, tile_rows=TZ_, graph_steps=G_, prefetch=PF_, prefetch_reverse=PR_,
-                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_, reverse_steps=RS_, forward_steps=FS_)
+                         shots_in_flight_reverse=SR_, tile_rows_reverse=TZR_, reverse_steps=RS_, forward_steps=FS_,
+                         graph_branches=GB_)
     else:
         ex = B.make_exec(autotune=1)
     pr = FWIProblem(grid, geom, w.wavelet, d_obs, "int", ex, illum=True, hmax=HM, device=dev)
@@ -542,7 +544,8 @@ def main():
                    "prefetch_reverse": chosen["prefetch_reverse"],
                    "shots_in_flight_reverse": chosen["shots_in_flight_reverse"],
                    "tile_rows_reverse": chosen["tile_rows_reverse"],
-                   "reverse_steps": chosen["reverse_steps"], "forward_steps": chosen["forward_steps"]},
+                   "reverse_steps": chosen["reverse_steps"], "forward_steps": chosen["forward_steps"],
+                   "graph_branches": chosen["graph_branches"]},
         "gcell_updates_per_s": cell_updates / (wall / args.steps) / 1e9,
         "phase_ms": {"forward_and_misfit": phase[0] / args.steps, "backward": rev_ms,
                      "precondition": phase[2] / args.steps},

@@ -151,6 +151,12 @@ typedef struct {
                                  1.  Not used with a free surface, in plain
                                  mode, for Born modelling or the forward-only
                                  calls                                         */
+    int32_t graph_branches;   /* independent launch chains that each captured
+                                 chunk of the two-step sweeps is split into,
+                                 each over a contiguous share of the launch's
+                                 shots, so that one chain's launches run in
+                                 the others' tails: 1 to 4 (at most the shots
+                                 per launch); 0 = 2                            */
 } fwi_exec;
 
 enum { FWI_EXEC_BATCHED = 0, FWI_EXEC_PLAIN = 1 };
@@ -181,7 +187,7 @@ size_t fwi_workspace_bytes(const fwi_grid *grid, const fwi_geometry *geom,
 
 /* The execution settings (shots_in_flight, tile_rows, graph_steps, prefetch,
  * prefetch_reverse, shots_in_flight_reverse, tile_rows_reverse,
- * reverse_steps) that a
+ * reverse_steps, forward_steps, graph_branches) that a
  * call with these arguments uses: the autotuned choice once tuning has run on
  * the current device, else the heuristic defaults.  Fills *chosen (mode and
  * autotune copied from exec).  Returns 0 or FWI_ERR_*. */

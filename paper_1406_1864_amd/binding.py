@@ -70,7 +70,8 @@ class fwi_exec(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("shots_in_flight", c_int32), ("tile_rows", c_int32),
                 ("graph_steps", c_int32), ("autotune", c_int32), ("prefetch", c_int32),
                 ("prefetch_reverse", c_int32), ("shots_in_flight_reverse", c_int32),
-                ("tile_rows_reverse", c_int32), ("reverse_steps", c_int32), ("forward_steps", c_int32)]
+                ("tile_rows_reverse", c_int32), ("reverse_steps", c_int32), ("forward_steps", c_int32),
+                ("graph_branches", c_int32)]
 
 
 _lib = None
@@ -174,10 +175,10 @@ class GeometryC:
 
 def make_exec(mode=EXEC_BATCHED, shots_in_flight=0, tile_rows=0, graph_steps=0, autotune=0,
               prefetch=0, prefetch_reverse=0, shots_in_flight_reverse=0, tile_rows_reverse=0,
-              reverse_steps=0, forward_steps=0) -> fwi_exec:
+              reverse_steps=0, forward_steps=0, graph_branches=0) -> fwi_exec:
     return fwi_exec(int(mode), int(shots_in_flight), int(tile_rows), int(graph_steps), int(autotune),
                     int(prefetch), int(prefetch_reverse), int(shots_in_flight_reverse), int(tile_rows_reverse),
-                    int(reverse_steps), int(forward_steps))
+                    int(reverse_steps), int(forward_steps), int(graph_branches))
 
 
 def _ptr(t):

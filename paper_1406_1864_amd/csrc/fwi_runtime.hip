@@ -150,6 +150,7 @@ struct Plan {
   int born = 0;                // Born perturbation wavefield buffers present
   int rev_steps = 1;           // time steps per launch of the plain reverse sweep (1 or 2)
   int fwd_steps = 1;           // time steps per launch of the gradient's forward sweep (1 or 2)
+  int branches = 1;            // independent chains per captured chunk of a two-step sweep
   int ulevels = kULevels, llevels = kLamLevels;
   int XT2 = 0;                 // tiles of the two-step reverse sweep along x
   double sp_a = 0.0;
@@ -186,12 +187,19 @@ struct Plan {
 // reverse sweep's time steps per launch (1 or 2).
 struct ExecChoice {
   int S, TZ, graph_steps, pf_fwd, pf_rev, Sr, TZr, rsteps, fsteps;
+  int branches = 0;  // independent chains per captured two-step chunk (0: kDefaultBranches)
 };
 
 std::mutex g_mutex;
 std::list<std::shared_ptr<Plan>> g_plans;  // most recent first
 std::map<std::vector<uint64_t>, ExecChoice> g_tuned;
 hipStream_t g_capture_stream = nullptr;
+// further capture streams and the fork/join events of chunks captured as
+// independent branches
+constexpr int kMaxBranches = 4;
+constexpr int kDefaultBranches = 2;
+hipStream_t g_branch_stream[kMaxBranches] = {};
+hipEvent_t g_fork = nullptr, g_join[kMaxBranches] = {};
 
 int shot_nt(const fwi_grid* g, const fwi_geometry* geo, int s) { return geo->nt ? geo->nt[s] : g->nt_max; }
 
@@ -294,6 +302,7 @@ std::shared_ptr<Plan> build_plan(const fwi_grid* g, const fwi_geometry* geo, con
   const bool fwd2 = (what == FWI_WS_GRADIENT || what == FWI_WS_AUTOGRAD || what == FWI_WS_EXTIMAGE) && !plain &&
                     !g->free_surface && ex.fsteps == 2;
   p->fwd_steps = fwd2 ? 2 : 1;
+  p->branches = ex.branches > 0 ? ex.branches : kDefaultBranches;
   p->ulevels = fwd2 ? 2 * kULevels : (rev2 ? kULevels2 : kULevels);
   p->llevels = rev2 ? kLamLevels2 : kLamLevels;
   p->XT2 = kWavesPerBlock * ((d.X + kBlk2 - 1) / kBlk2);
@@ -554,6 +563,40 @@ hipError_t get_capture_stream(hipStream_t* out) {
   return hipSuccess;
 }
 
+// streams 1 .. n-1 for the branches of a captured chunk, and the events
+hipError_t get_branch_streams(int n) {
+  if (!g_fork) {
+    hipError_t e = hipEventCreateWithFlags(&g_fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  for (int i = 1; i < n; ++i) {
+    if (!g_branch_stream[i]) {
+      hipError_t e = hipStreamCreateWithFlags(&g_branch_stream[i], hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    if (!g_join[i]) {
+      hipError_t e = hipEventCreateWithFlags(&g_join[i], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// slots s0 .. s0 + n - 1 of a launch as a launch of their own (the per-slot
+// arrays of the reverse sweep move with them)
+StepArgs slot_range(const StepArgs& a, int s0, int n) {
+  StepArgs b = a;
+  b.S = n;
+  b.xcd_map = (n >= 8 && n % 8 == 0) ? a.xcd_map : 0;
+  b.slots += s0;
+  b.lam += (int64_t)s0 * a.lstride;
+  b.g += (int64_t)s0 * a.d.model;
+  b.E += (int64_t)s0 * a.d.model;
+  if (b.ext_lam) b.ext_lam += (int64_t)s0 * a.ext_T * a.d.model;
+  if (b.ext_D) b.ext_D += (int64_t)s0 * a.ext_T * a.d.model;
+  return b;
+}
+
 // Run `nsteps` time steps of one phase for one batch: direct launches, or
 // replays of a captured chunk of `graph_steps` launches that read the step
 // base from the workspace header.
@@ -602,7 +645,10 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   }
   if (ext && p.ext_T != T * spl) return fail(FWI_ERR_STATE, "extended-image ring differs from the graph chunk");
   int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
-  const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T,
+  // chunks of the two-step sweeps as two independent branches over half the
+  // slots each, so that one branch's launches fill the other's tails
+  const int nbr = two ? std::max(1, std::min({p.branches, a.S, kMaxBranches})) : 1;
+  const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T, (uint64_t)nbr,
                                       (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
                                       (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
                                       (uint64_t)wstride, (uint64_t)ext, (uint64_t)two};
@@ -613,12 +659,40 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   } else {
     hipStream_t cs;
     HIP_TRY(get_capture_stream(&cs));
+    if (nbr > 1) HIP_TRY(get_branch_streams(nbr));
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
     a.step_ctr = ctr;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < T && le == hipSuccess; ++k) {
-      a.step = k;
-      le = launch(a, cs);
+    if (nbr > 1) {
+      // independent chains over consecutive ranges of the slots
+      StepArgs ab[kMaxBranches];
+      hipStream_t sb[kMaxBranches] = {cs};
+      for (int i = 0; i < nbr; ++i) {
+        const int s0 = a.S * i / nbr, s1 = a.S * (i + 1) / nbr;
+        ab[i] = slot_range(a, s0, s1 - s0);
+        if (i) sb[i] = g_branch_stream[i];
+      }
+      le = hipEventRecord(g_fork, cs);
+      int forked = 1;  // streams that are part of the capture
+      while (le == hipSuccess && forked < nbr) {
+        le = hipStreamWaitEvent(sb[forked], g_fork, 0);
+        if (le == hipSuccess) ++forked;
+      }
+      for (int k = 0; k < T && le == hipSuccess; ++k)
+        for (int i = 0; i < nbr && le == hipSuccess; ++i) {
+          ab[i].step = k;
+          le = launch(ab[i], sb[i]);
+        }
+      for (int i = 1; i < forked; ++i) {
+        hipError_t je = hipEventRecord(g_join[i], sb[i]);
+        if (je == hipSuccess) je = hipStreamWaitEvent(cs, g_join[i], 0);
+        if (le == hipSuccess) le = je;
+      }
+    } else {
+      for (int k = 0; k < T && le == hipSuccess; ++k) {
+        a.step = k;
+        le = launch(a, cs);
+      }
     }
     if (ext && le == hipSuccess) {
       ExtArgs ec = e;
@@ -862,7 +936,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       // each candidate runs in a plan of its own layout (the two-step forward
       // sweep has twice the wavefield levels)
       auto prepare = [&](int fs) -> std::shared_ptr<Plan> {
-        ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max, fs};
+        ExecChoice c{S, TZ, best.graph_steps, PFs[0], RFs[0], S, TZ, rs_max, fs, best.branches};
         auto p = build_plan(g, geo, c, 0, what, 0);
         if (p->L.total > ws_bytes) return nullptr;
         if (begin_call(*p, ws, v, s) != FWI_OK) return nullptr;
@@ -914,12 +988,16 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   }
   if (F.empty()) return FWI_OK;  // nothing fitted the workspace: keep the defaults
   // near-ties (within the 2 % below) go to the reverse settings that move the
-  // fewest bytes per step: two steps per launch, then more shots per launch.
+  // fewest bytes per step: two steps per launch, then more shots per launch,
+  // then taller bands (fewer overlap rows read twice).
   // A short timing flatters the one-step sweep: it leaves out the slower
   // restart launches, and its small working set reuses the previous launch's
   // fields from the Infinity Cache more than over a whole sweep.
-  std::stable_sort(Rv.begin(), Rv.end(),
-                   [](const Cand& x, const Cand& y) { return x.rs > y.rs || (x.rs == y.rs && x.S > y.S); });
+  std::stable_sort(Rv.begin(), Rv.end(), [](const Cand& x, const Cand& y) {
+    if (x.rs != y.rs) return x.rs > y.rs;
+    if (x.S != y.S) return x.S > y.S;
+    return x.TZ > y.TZ;
+  });
   // the same for the forward: two steps per launch, more shots, then longer
   // bands (fewer halo rows read twice)
   std::stable_sort(F.begin(), F.end(), [](const Cand& x, const Cand& y) {
@@ -971,6 +1049,7 @@ ExecChoice base_choice(const fwi_grid* g, const fwi_geometry* geo, const fwi_exe
   c.TZr = (ex && ex->tile_rows_reverse > 0) ? ex->tile_rows_reverse : 0;
   c.rsteps = (ex && ex->reverse_steps > 0) ? ex->reverse_steps : 1;
   c.fsteps = (ex && ex->forward_steps > 0) ? ex->forward_steps : 1;
+  c.branches = (ex && ex->graph_branches > 0) ? ex->graph_branches : kDefaultBranches;
   return c;
 }
 
@@ -988,7 +1067,8 @@ std::vector<uint64_t> tune_key(const fwi_grid* g, const fwi_geometry* geo, const
                              (uint64_t)(ex ? ex->shots_in_flight_reverse : 0),
                              (uint64_t)(ex ? ex->tile_rows_reverse : 0),
                              (uint64_t)(ex ? ex->reverse_steps : 0),
-                             (uint64_t)(ex ? ex->forward_steps : 0)};
+                             (uint64_t)(ex ? ex->forward_steps : 0),
+                             (uint64_t)(ex ? ex->graph_branches : 0)};
   int ntmax = 0, nrmax = 0;
   for (int s = 0; s < geo->nshot; ++s) {
     ntmax = std::max(ntmax, shot_nt(g, geo, s));
@@ -1075,6 +1155,8 @@ int check_exec(const fwi_exec* ex) {
     return fail(FWI_ERR_ARG, "prefetch_reverse must be 0, 1 or 3");
   if (ex && (ex->reverse_steps < 0 || ex->reverse_steps > 2)) return fail(FWI_ERR_ARG, "reverse_steps must be 0, 1 or 2");
   if (ex && (ex->forward_steps < 0 || ex->forward_steps > 2)) return fail(FWI_ERR_ARG, "forward_steps must be 0, 1 or 2");
+  if (ex && (ex->graph_branches < 0 || ex->graph_branches > kMaxBranches))
+    return fail(FWI_ERR_ARG, "graph_branches must be in [0, 4]");
   return FWI_OK;
 }
 
@@ -1084,6 +1166,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   const int plain = ex && ex->mode == FWI_EXEC_PLAIN;
   if (int rc = check_exec(ex)) return rc;
   ExecChoice c = base_choice(g, geo, ex);
+  const int branches = c.branches;  // not tuned: the tuner times with it
   const bool tune = !plain && ex && ex->autotune && !sizing_only;
   const uint64_t ikey = inputs_hash(g, geo);
   std::lock_guard<std::mutex> lock(g_mutex);
@@ -1113,6 +1196,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
       c = t;
     }
   }
+  c.branches = branches;
   Hasher h;
   h.pod(ikey);
   h.pod(what == FWI_WS_AUTOGRAD ? FWI_WS_AUTOGRAD : what);
@@ -1126,6 +1210,7 @@ int get_plan(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
   h.pod(c.TZr);
   h.pod(c.rsteps);
   h.pod(c.fsteps);
+  h.pod(c.branches);
   h.pod(ext_h);
   const uint64_t key = h.h;
   for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
@@ -1398,6 +1483,7 @@ int fwi_exec_query(const fwi_grid* grid, const fwi_geometry* geom, const fwi_exe
                              what == FWI_WS_BORN || what == FWI_WS_GNHVP)
                                 ? 1
                                 : c.fsteps;
+    chosen->graph_branches = plain ? 1 : (exec && exec->graph_branches > 0 ? exec->graph_branches : kDefaultBranches);
   }
   return FWI_OK;
 }

@@ -188,6 +188,14 @@ def test_reverse_launch_settings(lib):
                             B.WS_GRADIENT)["forward_steps"] == 1
     with pytest.raises(B.FwiError):
         B.fwi_exec_query(w.grid, w.geom, B.make_exec(forward_steps=3), B.WS_GRADIENT)
+    # independent launch chains per captured chunk: two unless set, one in plain mode
+    assert B.fwi_exec_query(w.grid, w.geom, B.make_exec(), B.WS_AUTOGRAD)["graph_branches"] == 2
+    for n in (1, 3, 4):
+        assert B.fwi_exec_query(w.grid, w.geom, B.make_exec(graph_branches=n), B.WS_AUTOGRAD)["graph_branches"] == n
+    assert B.fwi_exec_query(w.grid, w.geom, B.make_exec(mode=B.EXEC_PLAIN), B.WS_GRADIENT)["graph_branches"] == 1
+    for bad in (-1, 5):
+        with pytest.raises(B.FwiError):
+            B.fwi_exec_query(w.grid, w.geom, B.make_exec(graph_branches=bad), B.WS_GRADIENT)
     a = B.fwi_workspace_bytes(w.grid, w.geom, B.make_exec(forward_steps=2), B.WS_GRADIENT)
     b = B.fwi_workspace_bytes(w.grid, w.geom, B.make_exec(forward_steps=1), B.WS_GRADIENT)
     assert a > b                          # two sets of wavefield levels

@@ -39,6 +39,12 @@ EXECS = {
     "both_two_step_graph": B.make_exec(shots_in_flight=4, shots_in_flight_reverse=2, tile_rows=12,
                                        tile_rows_reverse=24, graph_steps=5, reverse_steps=2, forward_steps=2,
                                        prefetch=3),
+    # graph chunks of the two-step sweeps as one launch chain, and as three
+    # chains over uneven shares of the shots (1, 2, 2 of the ragged case's 5)
+    "two_step_one_chain": B.make_exec(shots_in_flight=4, tile_rows=16, tile_rows_reverse=16, graph_steps=5,
+                                      reverse_steps=2, forward_steps=2, graph_branches=1),
+    "two_step_three_chains": B.make_exec(shots_in_flight=5, tile_rows=16, tile_rows_reverse=8, graph_steps=3,
+                                         reverse_steps=2, forward_steps=2, graph_branches=3),
 }
 
 
