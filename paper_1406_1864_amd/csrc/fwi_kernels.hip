@@ -635,6 +635,7 @@ __global__ __launch_bounds__(256) void k_reverse(StepArgs a) {
 // row, so that a load costs no per-lane address arithmetic.  The resource
 // covers the array; every offset used here stays inside it.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kCachePolicyNT = 2;  // the nt bit of a gfx950 buffer access's cache policy
 __device__ __forceinline__ rsrc_t make_rsrc(const float* base, int64_t floats) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)(floats * 4), 0x00020000);
 }
@@ -643,6 +644,15 @@ __device__ __forceinline__ float bld(rsrc_t r, uint32_t voff, int32_t soff) {
 }
 __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, 0);
+}
+// the same with the non-temporal hint (nt), for results that no later access
+// of the launch reads, so that they do not displace the input lines that the
+// launch's neighbouring bands and workgroups still read from L2 (the reverse
+// sweep's stores: its launch time fell 1.2 % at 2048x768 and 2.7 % at
+// 1024x384; the forward sweep's ran 4.7 % slower with it, and the hint on
+// the reverse's g and E loads cost 7.5 %)
+__device__ __forceinline__ void bst_nt(rsrc_t r, uint32_t voff, int32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, kCachePolicyNT);
 }
 
 // Two-step sweeps: the grid's last column block may own fewer than 248
@@ -899,8 +909,8 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
           }
         }
         if (z >= z0 && z < z1 && own_col) {
-          bst(rU, oc, ouO0 + z * P4, uo_);
-          bst(rL, oc, olO0 + z * P4, lo_);
+          bst_nt(rU, oc, ouO0 + z * P4, uo_);
+          bst_nt(rL, oc, olO0 + z * P4, lo_);
           if (EXT && z >= mz_lo && z < mz_hi && col.mcol) {
             const int64_t mi = (int64_t)(z - d.N) * d.nx + col.mx;
             xlA[mi] = lo_;
@@ -955,12 +965,12 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
             st_u = st_l && strip_index(row, col) >= 0;
           }
         }
-        if (st_l) bst(rL, oc, olO1 + zbB * P4, l1);
-        if (st_u) bst(rU, oc, ouO1 + zbB * P4, u1);
+        if (st_l) bst_nt(rL, oc, olO1 + zbB * P4, l1);
+        if (st_u) bst_nt(rU, oc, ouO1 + zbB * P4, u1);
         if (st_g) {
           const int32_t mo = mrow4(zbB);
-          bst(rG, om, mo, gn);
-          bst(rG, om, mo + oE, en);
+          bst_nt(rG, om, mo, gn);
+          bst_nt(rG, om, mo + oE, en);
           if (EXT && hasB) {  // (st_g: a model cell of this wavefront)
             const int64_t mi = (int64_t)(zbB - d.N) * d.nx + col.mx;
             xlB[mi] = l1;
