@@ -194,6 +194,7 @@ std::mutex g_mutex;
 std::list<std::shared_ptr<Plan>> g_plans;  // most recent first
 std::map<std::vector<uint64_t>, ExecChoice> g_tuned;
 hipStream_t g_capture_stream = nullptr;
+std::mutex g_capture_mutex;  // graph capture (run_steps)
 // further capture streams and the fork/join events of chunks captured as
 // independent branches
 constexpr int kMaxBranches = 4;
@@ -653,6 +654,9 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
                                       (uint64_t)(uintptr_t)ws, (uint64_t)(uintptr_t)wavelet,
                                       (uint64_t)wstride, (uint64_t)ext, (uint64_t)two};
   hipGraphExec_t exec = nullptr;
+  // the capture streams, the fork and join events and the plan's graph cache
+  // are shared by calls from every thread
+  std::unique_lock<std::mutex> capture_lock(g_capture_mutex);
   auto it = p.graphs.find(gkey);
   if (it != p.graphs.end()) {
     exec = it->second;
@@ -714,6 +718,7 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
     if (ie != hipSuccess) return fail(FWI_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     p.graphs[gkey] = exec;
   }
+  capture_lock.unlock();
   // whole chunks as graph replays, the remainder as direct launches, so that
   // every launch advances at least one shot
   const int full = nsteps / T;

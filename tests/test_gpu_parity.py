@@ -217,6 +217,42 @@ def test_launch_chains_give_the_same_bits(call):
             assert torch.equal(x, y), (call, nb, k)
 
 
+def test_calls_from_two_threads_on_two_streams():
+    """Two host threads call fwi_gradient at the same time, each on a stream and
+    a workspace of its own (both capture their graph chunks in that call):
+    each result has the bits of the same call made alone."""
+    import threading
+    grid, geom, v_true, v_start, wav = ragged_geometry()
+    d_obs = random_traces(geom, grid.nt_max, seed=9, scale=1e-3)
+    ex = B.make_exec(shots_in_flight=5, tile_rows=16, tile_rows_reverse=16, graph_steps=4, reverse_steps=2,
+                     forward_steps=2)
+    ref = B.gradient(v_start, wav, grid, geom, d_obs, "int", ex, hmax=2)
+    torch.cuda.synchronize()
+    out, errors = [None, None], []
+    start = threading.Barrier(2)
+
+    def work(i):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                start.wait(timeout=60)
+                out[i] = B.gradient(v_start, wav, grid, geom, d_obs, "int", ex, hmax=2)
+            stream.synchronize()
+        except Exception as e:  # reported in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,), daemon=True) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for o in out:
+        assert o is not None
+        for x, y in zip(ref, o):
+            assert torch.equal(x, y)
+
+
 def test_no_shots_gives_zero():
     grid, geom, v_true, v_start, wav = ragged_geometry()
     empty = Geometry(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(1, np.int32), np.zeros(0, np.int32),
