@@ -12,20 +12,21 @@
 // P[k][cell] += C[2k][cell]^2 + C[2k+1][cell]^2 of every run is folded into
 // the last chunk's epilogue.
 //
-// Tiling (one workgroup of 8 wavefronts per CU, 108 KB of LDS):
-//   * a workgroup owns 256 columns c (128 bins) x 128 cells and loops over
+// Tiling (one workgroup of 8 wavefronts per CU, 144 KB of LDS):
+//   * a workgroup owns 256 columns c (128 bins) x 256 cells and loops over
 //     the runs of the launch and over the chunk's slabs of 32 time steps;
-//     wavefront w computes 64 columns x 64 cells as 4 x 4 tiles of 16 x 16
+//     wavefront w computes 128 columns x 64 cells as 8 x 4 tiles of 16 x 16
 //     with v_mfma_f32_16x16x32_bf16 (or v_mfma_f32_16x16x4_f32), so that each
-//     operand read from LDS feeds 4 tiles;
-//   * slabs are double-buffered in LDS and the series' loads are issued two
-//     slabs ahead into registers: while the matrix cores work on slab j, the
-//     loads of slabs j+1 and j+2 are in flight, one barrier per slab;
+//     column operand read from LDS feeds 4 tiles and each cell operand 8;
+//   * slabs are double-buffered in LDS and the series' loads are issued one
+//     slab ahead into registers: while the matrix cores work on slab j, the
+//     loads of slab j+1 are in flight, one barrier per slab (two slabs in
+//     flight would not fit the 256 registers the tile leaves);
 //   * the DFT matrix never crosses HBM or L2 in the loop: each slab's 256
 //     columns are generated into LDS from a fixed table of the 32 in-slab
 //     phases (held in registers) and one phase per bin and slab;
 //   * the series arrive time-major (cells contiguous, as the sweep writes
-//     them); each thread gathers 8 time steps of one cell and stores them
+//     them); each thread gathers 16 time steps of one cell and stores them
 //     cell-major into LDS, so that every MFMA operand is one 16-byte LDS read
 //     per lane; rows are padded to 144 bytes (conflict-free 16-byte reads);
 //   * the bf16 split keeps x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) for
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
   const int bt = q % nbt, ct = (q / nbt) * 8 + xcd;
   if (ct >= a.ntile) return;  // whole workgroup: no barrier is left waiting
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wc = wave & 3, wn = wave >> 2;        // 64-column quarter, 64-cell half
+  const int wc = wave & 1, wn = wave >> 1;        // 128-column half, 64-cell quarter
   const int lr = lane & 15, lq = lane >> 4;       // MFMA row / k group of the lane
   const int64_t cell0 = (int64_t)ct * kDftCells;
   const int c0 = bt * kDftCols;
@@ -99,46 +100,43 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
       tsin[2 * i + 1] = v.w;
     }
   }
-  // loader role: X - 8 of the slab's 32 steps of one cell
-  const int xc = tid & (kDftCells - 1), xq = __builtin_amdgcn_readfirstlane(tid >> 7);  // xq: per wavefront
+  // loader role: X - 16 of the slab's 32 steps of one cell
+  const int xc = tid & (kDftCells - 1), xq = __builtin_amdgcn_readfirstlane(tid >> 8);  // xq: per wavefront
   const int64_t gcell = cell0 + xc;
   const bool cell_ok = gcell < a.model;
   struct Stage {
-    float x[8];
+    float x[16];
     float2 ph;  // (cos, sin) of the slab's phase for bin kg
   };
-  Stage s0, s1;  // two slabs' loads in flight: a slab is issued two slabs before it is stored
+  Stage s0;  // the next slab's loads, in flight while the current slab is multiplied
 
-  // loads are issued unconditionally (a slab past the chunk's end re-reads
-  // the last one and is never stored), so that the number of loads in
-  // flight is the same on every path and each wait covers exactly the slab
-  // that is about to be stored; they go through buffer resources with a
-  // wave-uniform base (the slab's rows of this wave, the slab's phases of
-  // the workgroup's bins), a per-lane offset fixed for the kernel and a
-  // uniform row offset, so that no address is computed per lane in the loop
+  // loads go through buffer resources with a wave-uniform base (the slab's
+  // rows of this wave, the slab's phases of the workgroup's bins), a per-lane
+  // offset fixed for the kernel and a uniform row offset, so that no address
+  // is computed per lane in the loop
   const uint32_t xoff = (uint32_t)(cell_ok ? xc : 0) * 4u;
   const uint32_t poff = (uint32_t)wk * 8u;
-  const int rows_bytes = (int)min<int64_t>(INT32_MAX, 8 * a.R * 4);
+  const int rows_bytes = (int)min<int64_t>(INT32_MAX, 16 * a.R * 4);  // the 16 rows a thread loads
   auto load = [&](Stage& st, int slot, int jr) {
     const int j = min(jr, a.nslab - 1);
     const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float2*>(a.Ph + (int64_t)(a.j0 + j) * a.Kp + c0 / 2), (short)0, kDftCols / 2 * 8, 0x00020000);
     st.ph = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rp, (int)poff, 0, 0));
-    // rows t0 .. t0 + 7 of this wave, clamped to the chunk's last step
-    const int t0 = min(j * kDftKT + 8 * xq, a.tc - 1);
+    // rows t0 .. t0 + 15 of this wave, clamped to the chunk's last step
+    const int t0 = min(j * kDftKT + 16 * xq, a.tc - 1);
     const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(a.X + (int64_t)slot * a.xslot + (int64_t)t0 * a.R + cell0), (short)0, rows_bytes,
         0x00020000);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 16; ++i) {
       const int r = min(t0 + i, a.tc - 1) - t0;
       st.x[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, (int)xoff, (int)(r * a.R * 4), 0));
     }
   };
   auto store = [&](Stage& st, int buf, int j) {
-    const int t0 = j * kDftKT + 8 * xq;
+    const int t0 = j * kDftKT + 16 * xq;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) st.x[i] = (cell_ok && t0 + i < a.tc) ? st.x[i] : 0.0f;
+    for (int i = 0; i < 16; ++i) st.x[i] = (cell_ok && t0 + i < a.tc) ? st.x[i] : 0.0f;
     uint8_t* A = lds[buf];
     uint8_t* B = lds[buf] + kStageW;
     // rows 2 wk (cosine) and 2 wk + 1 (sine), steps wt .. wt + 7
@@ -152,32 +150,36 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
     uint8_t* rs = rc + kPitch;
     uint8_t* row = B + xc * kPitch;
     if (SPLIT) {
-      uint32_t ch[4], cl[4], sh[4], sl[4], xh[4], xl[4];
+      uint32_t ch[4], cl[4], sh[4], sl[4], xh[8], xl[8];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         split2(wc8[2 * i], wc8[2 * i + 1], ch[i], cl[i]);
         split2(ws8[2 * i], ws8[2 * i + 1], sh[i], sl[i]);
-        split2(st.x[2 * i], st.x[2 * i + 1], xh[i], xl[i]);
       }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) split2(st.x[2 * i], st.x[2 * i + 1], xh[i], xl[i]);
       *(uint4*)(rc + 2 * wt) = make_uint4(ch[0], ch[1], ch[2], ch[3]);
       *(uint4*)(rc + 64 + 2 * wt) = make_uint4(cl[0], cl[1], cl[2], cl[3]);
       *(uint4*)(rs + 2 * wt) = make_uint4(sh[0], sh[1], sh[2], sh[3]);
       *(uint4*)(rs + 64 + 2 * wt) = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-      *(uint4*)(row + 16 * xq) = make_uint4(xh[0], xh[1], xh[2], xh[3]);
-      *(uint4*)(row + 64 + 16 * xq) = make_uint4(xl[0], xl[1], xl[2], xl[3]);
+      *(uint4*)(row + 32 * xq) = make_uint4(xh[0], xh[1], xh[2], xh[3]);
+      *(uint4*)(row + 32 * xq + 16) = make_uint4(xh[4], xh[5], xh[6], xh[7]);
+      *(uint4*)(row + 64 + 32 * xq) = make_uint4(xl[0], xl[1], xl[2], xl[3]);
+      *(uint4*)(row + 64 + 32 * xq + 16) = make_uint4(xl[4], xl[5], xl[6], xl[7]);
     } else {
       *(float4*)(rc + 4 * wt) = make_float4(wc8[0], wc8[1], wc8[2], wc8[3]);
       *(float4*)(rc + 4 * wt + 16) = make_float4(wc8[4], wc8[5], wc8[6], wc8[7]);
       *(float4*)(rs + 4 * wt) = make_float4(ws8[0], ws8[1], ws8[2], ws8[3]);
       *(float4*)(rs + 4 * wt + 16) = make_float4(ws8[4], ws8[5], ws8[6], ws8[7]);
-      *(float4*)(row + 32 * xq) = make_float4(st.x[0], st.x[1], st.x[2], st.x[3]);
-      *(float4*)(row + 32 * xq + 16) = make_float4(st.x[4], st.x[5], st.x[6], st.x[7]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        *(float4*)(row + 64 * xq + 16 * i) = make_float4(st.x[4 * i], st.x[4 * i + 1], st.x[4 * i + 2], st.x[4 * i + 3]);
     }
   };
 
-  floatx4 acc[4][4];
+  floatx4 acc[8][4];
   auto compute = [&](int buf) {
-    const uint8_t* A = lds[buf] + (wc * 64 + lr) * kPitch;
+    const uint8_t* A = lds[buf] + (wc * 128 + lr) * kPitch;
     const uint8_t* B = lds[buf] + kStageW + (wn * 64 + lr) * kPitch;
     if (SPLIT) {
       bf16x8 bh[4], bl[4];
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
         bl[n] = __builtin_bit_cast(bf16x8, *(const uint4*)(B + n * 16 * kPitch + 64 + lq * 16));
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 8; ++m) {
         const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(A + m * 16 * kPitch + lq * 16));
         const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(A + m * 16 * kPitch + 64 + lq * 16));
 #pragma unroll
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
         bv[n][1] = *(const float4*)(B + n * 16 * kPitch + lq * 32 + 16);
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 8; ++m) {
         const float4 a0 = *(const float4*)(A + m * 16 * kPitch + lq * 32);
         const float4 a1 = *(const float4*)(A + m * 16 * kPitch + lq * 32 + 16);
         const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
@@ -225,19 +227,18 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
   for (int slot = 0; slot < a.nslots; ++slot) {
     // the first two slabs' loads go out before the running spectra's
     load(s0, slot, 0);
-    load(s1, slot, 1);
     // the run's spectra, lane row pointer: the wavefront's 16 rows (m, i)
     // are walked by pointer increments, its 4 cell tiles are immediate offsets
-    float* Cs = a.C + (int64_t)slot * a.Cp * a.R + (int64_t)(c0 + wc * 64 + 4 * lq) * a.R + cell0 + wn * 64 + lr;
+    float* Cs = a.C + (int64_t)slot * a.Cp * a.R + (int64_t)(c0 + wc * 128 + 4 * lq) * a.R + cell0 + wn * 64 + lr;
     if (a.first) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 8; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     } else {
       const float* row = Cs;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 8; ++m) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -249,25 +250,20 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
     }
     store(s0, 0, 0);
     __syncthreads();
-    // slab j is in LDS buffer j & 1 and slab j + 1 in registers; slab j + 2
-    // is issued before slab j is multiplied (two iterations per pass, so that
-    // the register stages are named statically)
-    for (int j = 0; j < a.nslab; j += 2) {
-      load(s0, slot, j + 2);
-      compute(0);
-      if (j + 1 < a.nslab) store(s1, 1, j + 1);
-      __syncthreads();
-      if (j + 1 >= a.nslab) break;
-      load(s1, slot, j + 3);
-      compute(1);
-      if (j + 2 < a.nslab) store(s0, 0, j + 2);
+    // slab j is in LDS buffer j & 1; slab j + 1 is loaded into registers
+    // while slab j is multiplied, and stored into the other buffer after it
+    for (int j = 0; j < a.nslab; ++j) {
+      const bool more = j + 1 < a.nslab;
+      if (more) load(s0, slot, j + 1);
+      compute(j & 1);
+      if (more) store(s0, (j + 1) & 1, j + 1);
       __syncthreads();
     }
     // epilogue: the spectra, or after the run's last chunk their powers
     if (!a.last) {
       float* row = Cs;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 8; ++m) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -280,17 +276,17 @@ __global__ __launch_bounds__(kThreads) void k_dft(DftArgs a) {
       // rows 2p, 2p + 1 of the lane's four are the cosine and sine of bin
       // kb + 8 m + p (P is padded to Kp bins x R cells: no lane is masked);
       // all 32 running sums of the lane are read before any is written back
-      const int kb = (c0 + wc * 64 + 4 * lq) / 2;
+      const int kb = (c0 + wc * 128 + 4 * lq) / 2;
       float* const p0 = a.P + (int64_t)kb * a.R + cell0 + wn * 64 + lr;
-      float old[4][2][4];
+      float old[8][2][4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 8; ++m)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
           for (int n = 0; n < 4; ++n) old[m][p][n] = p0[(int64_t)(8 * m + p) * a.R + n * 16];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 8; ++m)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll

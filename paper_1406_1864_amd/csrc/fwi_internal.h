@@ -216,7 +216,7 @@ hipError_t launch_traces_out(const float* traces, int ntrace, int nt_max, const 
 // cosine and sine rows of kDftCols / 2 bins) by kDftCells model cells and
 // walks the time steps kDftKT at a time.
 constexpr int kDftCols = 256;
-constexpr int kDftCells = 128;
+constexpr int kDftCells = 256;
 constexpr int kDftKT = 32;
 
 struct DftArgs {
