@@ -648,12 +648,13 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, int32_t soff, float
 // the same with the non-temporal hint (nt), for results that no later access
 // of the launch reads, so that they do not displace the input lines that the
 // launch's neighbouring bands and workgroups still read from L2 (the reverse
-// sweep's stores: its launch time fell 1.2 % at 2048x768 and 2.7 % at
-// 1024x384; the forward sweep's ran 4.7 % slower with it, and the hint on
-// the reverse's g and E loads cost 7.5 %)
+// sweep's wavefield stores: its launch time fell 1.8 % at 2048x768 and 3.3 %
+// at 1024x384; with the hint on its g and E stores as well 0.4 % less, on
+// the forward sweep's stores 4.7 % slower, on loads slower in every case)
 __device__ __forceinline__ void bst_nt(rsrc_t r, uint32_t voff, int32_t soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, soff, kCachePolicyNT);
 }
+
 
 // Two-step sweeps: the grid's last column block may own fewer than 248
 // columns.  Its workgroup lanes at or past (owned columns + 8) feed nothing
@@ -969,8 +970,8 @@ __global__ __launch_bounds__(256, 4) void k_reverse2(StepArgs a) {
         if (st_u) bst_nt(rU, oc, ouO1 + zbB * P4, u1);
         if (st_g) {
           const int32_t mo = mrow4(zbB);
-          bst_nt(rG, om, mo, gn);
-          bst_nt(rG, om, mo + oE, en);
+          bst(rG, om, mo, gn);
+          bst(rG, om, mo + oE, en);
           if (EXT && hasB) {  // (st_g: a model cell of this wavefront)
             const int64_t mi = (int64_t)(zbB - d.N) * d.nx + col.mx;
             xlB[mi] = l1;
