@@ -646,8 +646,9 @@ int run_steps(Plan& p, void* ws, int batch, int phase, int flags, int nsteps, co
   }
   if (ext && p.ext_T != T * spl) return fail(FWI_ERR_STATE, "extended-image ring differs from the graph chunk");
   int32_t* ctr = &at<Header>(ws, p.L.hdr)->step;
-  // chunks of the two-step sweeps as two independent branches over half the
-  // slots each, so that one branch's launches fill the other's tails
+  // chunks of the two-step sweeps as `branches` independent chains over
+  // shares of the slots, so that one chain's launches fill the others' tails
+  // (the one-step sweeps' chunks stay one chain)
   const int nbr = two ? std::max(1, std::min({p.branches, a.S, kMaxBranches})) : 1;
   const std::vector<uint64_t> gkey = {(uint64_t)phase, (uint64_t)flags, (uint64_t)batch, (uint64_t)T, (uint64_t)nbr,
                                       (uint64_t)(phase == kPhaseFwd ? p.pf_fwd : p.pf_rev),
