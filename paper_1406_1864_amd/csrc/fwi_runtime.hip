@@ -914,17 +914,23 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     FSs = {1};
   else FSs = {2, 1};
   const int fwd_flags = grad ? (kFwdRecord | kFwdCkpt) : (what == FWI_WS_HESSIAN ? kFwdIllum : kFwdRecord);
-  const int nsteps = 32;
+  const int nsteps = 32;  // launches timed per candidate
   // FWI_TUNE_LOG set: each candidate's best time goes to stderr
   const bool tune_log = getenv("FWI_TUNE_LOG") != nullptr;
-  // best of two timings of `nsteps` launches, to keep the choice stable
+  // ms per time step, best of two timings of `nsteps` launches (two time
+  // steps each for the two-step sweeps, so that they run as the chunk of
+  // graph replays in launch chains they run as in a sweep, not as direct
+  // launches), to keep the choice stable
   auto timed = [&](Plan& p, int flags, int phase) {
-    return std::min(time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s),
-                    time_steps(p, ws, flags, phase, nsteps, wavelet, wstride, s));
+    const bool two = phase == kPhaseRev ? (flags == 0 && p.rev_steps == 2)
+                                        : (flags == (kFwdRecord | kFwdCkpt) && p.fwd_steps == 2);
+    const int n = two ? 2 * nsteps : nsteps;
+    return std::min(time_steps(p, ws, flags, phase, n, wavelet, wstride, s),
+                    time_steps(p, ws, flags, phase, n, wavelet, wstride, s)) / n;
   };
   struct Cand {
     int S, TZ, pf, rs, fs;
-    double per_shot;  // ms per shot and step
+    double per_shot;  // ms per shot and time step
   };
   std::vector<Cand> F, Rv;
   std::vector<int> TZs = TZf;
@@ -972,7 +978,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
         F.push_back(Cand{S, TZ, fpf, 1, ffs, fb / shots});
         if (tune_log)
           fprintf(stderr, "[fwi tune] forward S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, fpf, ffs,
-                  1e3 * fb / shots / nsteps);
+                  1e3 * fb / shots);
       }
       if (tr) {
         double rb = 1e30;
@@ -988,7 +994,7 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
         Rv.push_back(Cand{S, TZ, rpf, rrs, 1, rb / shots});
         if (tune_log)
           fprintf(stderr, "[fwi tune] reverse S %d TZ %d PF %d steps %d: %.3f us per shot-step\n", S, TZ, rpf, rrs,
-                  1e3 * rb / shots / nsteps);
+                  1e3 * rb / shots);
       }
     }
   }
@@ -1011,26 +1017,37 @@ int autotune(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, int
     if (x.S != y.S) return x.S > y.S;
     return x.TZ > y.TZ;
   });
-  // the pair with the least time per shot, the reverse's shots in flight
-  // dividing the forward's (any size in the autograd split); a later pair
-  // must be 2 % faster to replace one
+  // per forward shots-in-flight value, the forward settings and the reverse
+  // settings (shots in flight dividing the forward's; any size in the
+  // autograd split), each the first of its candidates in the orders above
+  // that no later one beats by 2 % on its own time; then the shots-in-flight
+  // value whose pair is fastest, a later (smaller) one having to be 2 % faster
   double best_t = 1e300;
   ExecChoice choice = best;
-  for (const Cand& f : F) {
+  std::vector<int> fS;  // forward shots-in-flight values, in F's order
+  for (const Cand& f : F)
+    if (std::find(fS.begin(), fS.end(), f.S) == fS.end()) fS.push_back(f.S);
+  for (int S : fS) {
+    const Cand* fb = nullptr;
+    for (const Cand& f : F)
+      if (f.S == S && (!fb || f.per_shot < fb->per_shot * 0.98)) fb = &f;
     if (!grad) {
-      if (f.per_shot < best_t * 0.98) {
-        best_t = f.per_shot;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, best.pf_rev, f.S, f.TZ, 1, 1};
+      if (fb->per_shot < best_t * 0.98) {
+        best_t = fb->per_shot;
+        choice = ExecChoice{fb->S, fb->TZ, best.graph_steps, fb->pf, best.pf_rev, fb->S, fb->TZ, 1, 1};
       }
       continue;
     }
+    const Cand* rb = nullptr;
     for (const Cand& r : Rv) {
-      if (what != FWI_WS_AUTOGRAD && (r.S > f.S || f.S % r.S)) continue;
-      const double t = f.per_shot + r.per_shot;
-      if (t < best_t * 0.98) {
-        best_t = t;
-        choice = ExecChoice{f.S, f.TZ, best.graph_steps, f.pf, r.pf, r.S, r.TZ, r.rs, f.fs};
-      }
+      if (what != FWI_WS_AUTOGRAD && (r.S > S || S % r.S)) continue;
+      if (!rb || r.per_shot < rb->per_shot * 0.98) rb = &r;
+    }
+    if (!rb) continue;
+    const double t = fb->per_shot + rb->per_shot;
+    if (t < best_t * 0.98) {
+      best_t = t;
+      choice = ExecChoice{fb->S, fb->TZ, best.graph_steps, fb->pf, rb->pf, rb->S, rb->TZ, rb->rs, fb->fs};
     }
   }
   (void)ikey;
