@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 from paper_1406_1864_amd import binding as B
+from paper_1406_1864_amd.synthetic import random_traces
 
 from helpers import GRAD_TOL, TRACE_TOL, J_TOL, max_rel, rel, report
 from test_gpu_parity import EXECS, cpu
@@ -103,3 +104,23 @@ def test_wide_extended_image(wide_ref, name):
     for h in range(2 * HMAX + 1):
         compare(f"image {tag} h={h - HMAX}", image[h], ref["I"][h], GRAD_TOL)
     columns(f"image {tag}", image, ref["I"], GRAD_TOL)
+
+
+@pytest.mark.parametrize("call", ["gradient", "extended_image"])
+def test_wide_launch_chains_give_the_same_bits(call):
+    """Three two-step workgroups wide: graph chunks in 2 and 3 independent
+    launch chains (shares of 1 + 2 and 1 + 1 + 1 of the 3 shots) give the
+    bits of one chain."""
+    grid, geom, v, wav = wide_case()
+    d_obs = random_traces(geom, grid.nt_max, seed=77, scale=1e-3)
+    outs = []
+    for nb in (1, 2, 3):
+        ex = B.make_exec(shots_in_flight=3, tile_rows=32, tile_rows_reverse=24, graph_steps=8, reverse_steps=2,
+                         forward_steps=2, graph_branches=nb)
+        if call == "gradient":
+            outs.append(B.gradient(v, wav, grid, geom, d_obs, "int", ex, hmax=HMAX))
+        else:
+            outs.append(B.extended_image(v, wav, grid, geom, d_obs, HMAX, "int", ex))
+    for nb, o in zip((2, 3), outs[1:]):
+        for k, (x, y) in enumerate(zip(outs[0], o)):
+            assert torch.equal(x, y), (call, nb, k)
