@@ -64,7 +64,8 @@ def parse():
                     help="also time the offset diagonal with the exact receiver term on the first "
                          "--exact-shots shots and EXACT_DIAG of their receivers (band to 4 f_peak)")
     ap.add_argument("--exact-shots", type=int, default=2)
-    ap.add_argument("--exact-sif", type=int, default=4, help="runs in flight of the exact offset diagonal")
+    ap.add_argument("--exact-sif", type=int, default=0,
+                    help="runs in flight of the exact offset diagonal (0 = the library's default)")
     ap.add_argument("--exact-dft", choices=["both", "fp32", "bf16x3"], default="both",
                     help="DFT arithmetic(s) timed for the exact offset diagonal")
     ap.add_argument("--exec", type=str, default="",
@@ -301,18 +302,20 @@ def time_offset_diag_exact(args, grid, geom, w, dev, full_shots):
                    (np.arange(ns + 1) * len(keep)).astype(np.int32),
                    np.tile(geom.rec_iz[keep], ns), np.tile(geom.rec_ix[keep], ns), geom.nt[:ns].copy())
     hmax, fmax = 16, 4.0 * w.f_peak
-    ex = B.make_exec(shots_in_flight=args.exact_sif)
+    Z, X = grid.padded
+    # runs in flight: the library's default (fwi.h) unless given
+    sif = args.exact_sif or (4 if Z * X >= 1_500_000 else 8)
+    ex = B.make_exec(shots_in_flight=sif)
     runs = ns + len(keep)
     nt = int(sub.nt[0])
     L = 2 * nt
     K = min(L // 2 + 1, int(np.floor(fmax * L * grid.dt + 1e-9)) + 1)
     model = grid.nz * grid.nx
-    Z, X = grid.padded
     dft_flop = 2.0 * model * (nt - 1) * 2 * K           # per run, FP32-equivalent
-    chunk = min(nt - 1, max(64, 8192 // min(args.exact_sif, runs) // 64 * 64))
+    chunk = min(nt - 1, max(64, 8192 // min(sif, runs) // 64 * 64))
     full_runs = full_shots + (b - a)
     out = {"unit": "runs/s (forward sweep with series capture + DFT on the matrix cores)", "shots": ns,
-           "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": args.exact_sif, "chunk": chunk,
+           "receivers": int(len(keep)), "hmax": hmax, "fmax_hz": fmax, "bins": K, "nt": nt, "runs_in_flight": sif, "chunk": chunk,
            "dft_shape_per_run": [model, 2 * K, nt - 1], "dft_tflop_per_run": dft_flop / 1e12,
            "cell_updates_per_run": float(Z * X * (nt - 1)), "full_problem_runs": full_runs}
     Dref = D = None

@@ -357,7 +357,8 @@ int fwi_misfit_backward(const fwi_grid *grid, const fwi_geometry *geom, const fw
  *
  * Shots are grouped by (record length, receiver set); each group costs one
  * forward run per receiver and per shot, shots_in_flight runs at a time
- * (default 4; of exec only shots_in_flight, tile_rows and prefetch are used:
+ * (default 4 on grids of at least 1.5 M padded cells, else 8; of exec only
+ * shots_in_flight, tile_rows and prefetch are used:
  * the sweeps are direct one-step launches, not graphs, and not autotuned).
  * A run's series are captured in FP32, 8192 / shots_in_flight updates at a
  * time (a multiple of 64, at least 64), and folded into its spectra by the

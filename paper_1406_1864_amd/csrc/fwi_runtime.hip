@@ -1300,9 +1300,15 @@ struct DxLayout {
 // updates (a multiple of 64) per chunk, so that fewer runs in flight buy
 // longer chunks and fewer read-modify-write passes over the spectra
 constexpr int kDxRunSteps = 8192;
-// default runs in flight (the forward sweeps of fewer runs leave the GPU
-// underused; more runs shorten the chunks)
-constexpr int kDxRuns = 4;
+// default runs in flight: the one-step capture sweeps of fewer runs leave
+// the GPU underused (at 1024 x 384, 8 runs cost 24 ms per run against 37 ms
+// with 4), more runs shorten the chunks (at 2048 x 768, 8 and 16 runs cost
+// 0.5 % and 18 % more than 4): 4 on grids of at least 1.5 M padded cells,
+// else 8
+int dx_default_runs(const fwi_grid* g) {
+  const int64_t cells = (int64_t)(g->nz + 2 * g->nsponge) * (g->nx + 2 * g->nsponge);
+  return cells >= 1500000 ? 4 : 8;
+}
 
 void dx_bins(int nt, double dt, double fmax, int& L, int& K, int& nyq) {
   L = 2 * nt;
@@ -1386,7 +1392,7 @@ int dx_layout(const fwi_grid* g, const fwi_geometry* geo, const fwi_exec* ex, in
   if (!(fmax >= 0) || !std::isfinite(fmax)) return fail(FWI_ERR_ARG, "fmax must be finite and >= 0");
   if (dft != FWI_DFT_FP32 && dft != FWI_DFT_BF16X3) return fail(FWI_ERR_ARG, "dft must be FWI_DFT_FP32 or FWI_DFT_BF16X3");
   const int64_t model = (int64_t)g->nz * g->nx;
-  const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : kDxRuns;
+  const int Sreq = (ex && ex->shots_in_flight > 0) ? ex->shots_in_flight : dx_default_runs(g);
   o = DxLayout{};
   int Smax = 1, nshot_max = 1;
   for (const DxGroup& gr : dx_groups(g, geo)) {
@@ -1847,7 +1853,7 @@ int fwi_offset_diag_exact(const fwi_grid* grid, const fwi_geometry* geom, const 
   // the impulse [1, 0, 0, ...] that starts a receiver's response
   HIP_TRY(launch_fill(imp, sizeof(float) * grid->nt_max, s));
   HIP_TRY(launch_set((int32_t*)imp, 0x3f800000, s));
-  const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : kDxRuns;
+  const int Sreq = (exec && exec->shots_in_flight > 0) ? exec->shots_in_flight : dx_default_runs(grid);
   for (const DxGroup& gr : groups) {
     const int Tn = gr.nt - 1;
     int L, K, nyq;
